@@ -1,0 +1,207 @@
+"""ADMM iterations for the projection QP, in FP64.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+The problem (Sec. III-A, eqs. (proj_cost)-(proj_boundary); Sec. III-D,
+eq. (compact_qp)), per joint and column (one sample of one joint):
+
+    x* = argmin_x 1/2 ||x - x~||^2   s.t.  x_1 = v0,  lo <= C x <= hi,
+
+with C, lo, hi the velocity-unit rows of ``problem.velocity_unit_rows``.
+
+Headline iteration ("admm"). The paper's splitting (Sec. III-D, "ADMM
+Solver"): a slack projection (Step 1, eq. (admm_zeta)), a primal solve with the
+pre-factored KKT matrix (Step 2, eqs. (admm_primal), (admm_KKT)), and a
+residual-driven multiplier update (Step 3, eq. (admm_dual)). As printed, the
+multiplier lives in the primal space and is absent from the slack step, which
+makes every feasible point a fixed point; this module therefore keeps the same
+three steps and the same factorization but carries the multiplier y in the
+constraint space (the standard scaled ADMM). Its fixed point is the exact
+projection. With relaxation alpha (1 = none) one iteration is
+
+    x+  = solution of M [x; mu] = [x~ + rho C^T (z - y/rho); v0]      (Step 2)
+    s^  = alpha C x+ + (1 - alpha) z
+    z+  = clip(s^ + y/rho, lo, hi)                                    (Step 1)
+    y+  = y + rho (s^ - z+)                                           (Step 3)
+
+started from x0 = x~ with x0_1 := v0, y0 = 0, z0 = clip(C x0) (or a supplied
+warm state (x_w, y_w): x0 = x_w with x0_1 := v0, z0 = clip(C x0 + y_w/rho)).
+
+Residuals (per column, velocity units, rad/s):
+    r_p = max_i |(C x)_i - z_i|                         primal feasibility gap
+    r_d = max_{k>=2} |x_k - x~_k + (C^T y)_k|           stationarity gap
+The stationarity row k = 1 is excluded because the equality multiplier mu of
+x_1 = v0 absorbs it.
+
+Early exit. Columns are grouped 16 samples of one joint at a time (samples
+16g .. 16g+15). With a tolerance, a group stops at the first check point
+(iteration 0, every ``check_every`` iterations, and ``max_iters``) where every
+column in it has max(r_p, r_d) <= tol.
+
+``literal_joint`` runs the iteration exactly as printed (paper scaling of G,
+delta = rho, primal-space lambda, dual step delta/2) for comparison only.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import problem
+from .factor import KKTFactor, penalty_matrix
+
+GROUP = 16
+
+
+@dataclasses.dataclass
+class JointResult:
+    x: np.ndarray        # (ncols, H)
+    r_p: np.ndarray      # (ncols,)
+    r_d: np.ndarray      # (ncols,)
+    iters: np.ndarray    # (ncols,) int
+    z: np.ndarray        # (ncols, 4H-1)
+    y: np.ndarray        # (ncols, 4H-1)
+
+
+def residuals(C, x, xt, z, y):
+    """(r_p, r_d) per column for states given as (rows, ncols) arrays."""
+    r_p = np.max(np.abs(C @ x - z), axis=0)
+    stat = x - xt + C.T @ y
+    r_d = np.max(np.abs(stat[1:]), axis=0) if x.shape[0] > 1 else np.zeros(x.shape[1])
+    return r_p, r_d
+
+
+def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
+               q0: float, v0: float, rho: float = 1.0, alpha: float = 1.0,
+               iters: int = 100, tol: Optional[float] = None, check_every: int = 10,
+               group: int = GROUP, warm_x: Optional[np.ndarray] = None,
+               warm_y: Optional[np.ndarray] = None) -> JointResult:
+    """Headline ADMM for the columns of one joint.
+
+    xt_cols: (ncols, H) samples x~. With ``tol`` None the iteration runs exactly
+    ``iters`` times; otherwise ``iters`` is the cap and groups stop early.
+    """
+    rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
+    C, lo, hi = rows.C, rows.lo[:, None], rows.hi[:, None]
+    fac = KKTFactor(penalty_matrix(C, rho))
+    xt = np.asarray(xt_cols, dtype=np.float64).T.copy()         # (H, ncols)
+    ncols = xt.shape[1]
+    x = (xt.copy() if warm_x is None else np.asarray(warm_x, dtype=np.float64).T.copy())
+    x[0, :] = v0
+    y = (np.zeros((C.shape[0], ncols)) if warm_y is None
+         else np.asarray(warm_y, dtype=np.float64).T.copy())
+    z = np.clip(C @ x + y / rho, lo, hi)
+
+    done = np.zeros(ncols, dtype=bool)
+    n_done = np.full(ncols, iters, dtype=np.int64)
+    gid = np.arange(ncols) // group
+    n_groups = int(gid.max()) + 1 if ncols else 0
+
+    def check(l):
+        if tol is None:
+            return
+        r_p, r_d = residuals(C, x, xt, z, y)
+        ok = np.maximum(r_p, r_d) <= tol
+        for g in range(n_groups):
+            m = gid == g
+            if not done[m].any() and ok[m].all():
+                done[m] = True
+                n_done[m] = l
+
+    check(0)
+    for l in range(1, iters + 1):
+        if done.all():
+            break
+        act = ~done
+        xa, za, ya = x[:, act], z[:, act], y[:, act]
+        r = xt[:, act] + rho * (C.T @ (za - ya / rho))
+        x_new = fac.solve(r, v0)
+        s = C @ x_new
+        shat = alpha * s + (1.0 - alpha) * za
+        z_new = np.clip(shat + ya / rho, lo, hi)
+        y_new = ya + rho * (shat - z_new)
+        x[:, act], z[:, act], y[:, act] = x_new, z_new, y_new
+        del xa
+        if l % check_every == 0 or l == iters:
+            check(l)
+    r_p, r_d = residuals(C, x, xt, z, y)
+    return JointResult(x=x.T.copy(), r_p=r_p, r_d=r_d, iters=n_done, z=z.T.copy(), y=y.T.copy())
+
+
+@dataclasses.dataclass
+class RequestResult:
+    x: np.ndarray        # [N][H][nj] float64
+    r_p: np.ndarray      # [N][nj]
+    r_d: np.ndarray      # [N][nj]
+    iters: np.ndarray    # [N][nj]
+    y: np.ndarray        # [N][nj][4H-1]
+
+
+def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
+                  rho: float = 1.0, alpha: float = 1.0, iters: int = 100,
+                  tol: Optional[float] = None, check_every: int = 10,
+                  warm_x: Optional[np.ndarray] = None,
+                  warm_y: Optional[np.ndarray] = None) -> RequestResult:
+    """Project every sample of a request (layout [N][H][nj]), joint by joint."""
+    samples = np.asarray(samples)
+    N, H_, nj = samples.shape
+    assert H_ == H
+    x = np.zeros((N, H, nj))
+    r_p = np.zeros((N, nj))
+    r_d = np.zeros((N, nj))
+    it = np.zeros((N, nj), dtype=np.int64)
+    y = np.zeros((N, nj, 4 * H - 1))
+    for j in range(nj):
+        lim = problem.joint_limits(bounds, j)
+        res = admm_joint(samples[:, :, j], H, dt, lim, float(q0[j]), float(v0[j]), rho=rho,
+                         alpha=alpha, iters=iters, tol=tol, check_every=check_every,
+                         warm_x=None if warm_x is None else warm_x[:, :, j],
+                         warm_y=None if warm_y is None else warm_y[:, j, :])
+        x[:, :, j] = res.x
+        r_p[:, j] = res.r_p
+        r_d[:, j] = res.r_d
+        it[:, j] = res.iters
+        y[:, j, :] = res.y
+    return RequestResult(x=x, r_p=r_p, r_d=r_d, iters=it, y=y)
+
+
+def shift_state(x: np.ndarray, y: np.ndarray, H: int):
+    """Warm start for the next MPC step: advance x and every row block of y by one
+    step, repeating the last entry of each block (x: [N][H][nj], y: [N][nj][4H-1])."""
+    xs = np.concatenate([x[:, 1:, :], x[:, -1:, :]], axis=1)
+    ys = np.empty_like(y)
+    for sl in problem.JointRows(C=None, lo=None, hi=None, H=H).blocks:
+        blk = y[:, :, sl]
+        ys[:, :, sl] = np.concatenate([blk[:, :, 1:], blk[:, :, -1:]], axis=2)
+    return xs, ys
+
+
+# ---------------------------------------------------------------------------
+# The iteration exactly as printed in the paper (comparison flag)
+# ---------------------------------------------------------------------------
+
+def literal_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
+                  q0: float, v0: float, delta: float = 1.0, iters: int = 100,
+                  x_init: Optional[np.ndarray] = None, lam_init: Optional[np.ndarray] = None):
+    """Sec. III-D, eqs. (admm_zeta), (admm_primal)/(admm_KKT), (admm_dual), verbatim.
+
+    G, h in the paper's physical scaling (eq. (G_h_def), one joint), penalty delta,
+    lambda in the primal space, lambda_0 = 0 and x_0 = x~ with x_1 := v0 unless
+    ``lam_init`` / ``x_init`` are given. Returns (x (ncols, H), max constraint
+    violation per column).
+    """
+    G, h = problem.per_joint_G_h(H, dt, lim, q0, v0)
+    fac = KKTFactor(np.eye(H) + delta * (G.T @ G))
+    xt = np.asarray(xt_cols, dtype=np.float64).T.copy()
+    x = xt.copy() if x_init is None else np.asarray(x_init, dtype=np.float64).T.copy()
+    x[0, :] = v0
+    lam = np.zeros_like(xt) if lam_init is None else np.asarray(lam_init, dtype=np.float64).T.copy()
+    hh = h[:, None]
+    for _ in range(iters):
+        zeta = np.maximum(0.0, hh - G @ x)                                  # Step 1
+        x = fac.solve(delta * (G.T @ (hh - zeta)) + lam + xt, v0)           # Step 2
+        lam = lam - 0.5 * delta * (G.T @ (G @ x - hh + zeta))               # Step 3
+    viol = np.maximum(0.0, np.max(G @ x - hh, axis=0))
+    return x.T.copy(), viol

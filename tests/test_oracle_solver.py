@@ -1,0 +1,257 @@
+"""Pins of the oracle's ADMM iteration and of the exact projection.
+
+The exact projection x* (Sec. III-A, eq. (proj_cost)) is pinned by brute-force
+face enumeration, KKT certificates, SLSQP, and closed-form special cases. The
+ADMM iterates at a fixed count have no printed values; they are pinned by the
+optimality conditions of each step and by convergence to x*.
+"""
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+from oracle import admm, exact, factor, problem
+import workloads as W
+
+
+def _lim(tight=True):
+    if tight:
+        return problem.JointLimits(-0.5, 0.6, -1.5, 1.4, -6.0, 7.0, -50.0, 40.0)
+    return problem.JointLimits(-1e6, 1e6, -1e6, 1e6, -1e9, 1e9, -1e12, 1e12)
+
+
+@pytest.mark.parametrize("H", [2, 3, 4, 5])
+def test_admm_converges_to_brute_force(H):
+    rng = np.random.default_rng(100 + H)
+    dt = 0.05
+    lim = _lim()
+    for trial in range(4):
+        q0 = rng.uniform(-0.3, 0.3)
+        v0 = rng.uniform(-1.0, 1.0)
+        xt = rng.normal(0.0, 2.5, H)
+        rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
+        xb = exact.brute_force(xt, rows.C, rows.lo, rows.hi, v0)
+        assert xb is not None
+        viol, stat = exact.kkt_certificate(xb, xt, rows.C, rows.lo, rows.hi, v0)
+        assert viol < 1e-9 and stat < 1e-9
+        res = admm.admm_joint(xt[None, :], H, dt, lim, q0, v0, iters=30000, tol=1e-11,
+                              check_every=50)
+        np.testing.assert_allclose(res.x[0], xb, atol=1e-8)
+        xs = exact.slsqp(xt, rows.C, rows.lo, rows.hi, v0)
+        np.testing.assert_allclose(xs, xb, atol=1e-6)
+
+
+def test_certificate_rejects_wrong_points():
+    """A perturbed optimum fails the certificate (the check is not vacuous)."""
+    rng = np.random.default_rng(5)
+    H, dt = 5, 0.05
+    lim = _lim()
+    xt = rng.normal(0, 2.5, H)
+    rows = problem.velocity_unit_rows(H, dt, lim, 0.1, 0.3)
+    xb = exact.brute_force(xt, rows.C, rows.lo, rows.hi, 0.3)
+    for k in range(1, H):
+        for eps in (1e-3, -1e-3):
+            x = xb.copy()
+            x[k] += eps
+            viol, stat = exact.kkt_certificate(x, xt, rows.C, rows.lo, rows.hi, 0.3, act_tol=1e-9)
+            assert viol > 1e-6 or stat > 1e-6
+
+
+@pytest.mark.parametrize("H,dt,N", [(20, 0.05, 24), (50, 0.02, 12)])
+def test_admm_converges_to_certified_projection(H, dt, N):
+    """At realistic sizes the converged iterate, polished on its active set, passes KKT."""
+    r = W.make_request(7, N=N, H=H, nj=2, dt=dt, kind="smooth" if H == 50 else "white")
+    for j in range(2):
+        lim = problem.joint_limits(r.bounds, j)
+        rows = problem.velocity_unit_rows(H, dt, lim, r.q0[j], r.v0[j])
+        res = admm.admm_joint(r.samples[:, :, j], H, dt, lim, r.q0[j], r.v0[j], iters=40000,
+                              tol=1e-10, check_every=100, alpha=1.6)
+        for c in range(N):
+            xt = r.samples[c, :, j].astype(np.float64)
+            xp = exact.polish(xt, rows.C, rows.lo, rows.hi, r.v0[j], res.y[c])
+            viol, stat = exact.kkt_certificate(xp, xt, rows.C, rows.lo, rows.hi, r.v0[j])
+            assert viol < 1e-8 and stat < 1e-8, (c, viol, stat)
+            np.testing.assert_allclose(res.x[c], xp, atol=1e-7)
+
+
+def test_loose_bounds_return_sample_with_boundary_velocity():
+    """All bounds inactive: x* = x~ with x_1 := v0 (closed form)."""
+    rng = np.random.default_rng(1)
+    H, dt = 15, 0.05
+    xt = rng.normal(0, 1, (9, H))
+    res = admm.admm_joint(xt, H, dt, _lim(False), 0.0, 0.25, iters=50)
+    want = xt.copy()
+    want[:, 0] = 0.25
+    np.testing.assert_allclose(res.x, want, atol=1e-12)
+
+
+def test_velocity_only_bounds_clip():
+    """Only velocity bounds finite: x*_k = clip(x~_k) for k >= 2, x*_1 = v0."""
+    rng = np.random.default_rng(2)
+    H, dt = 12, 0.05
+    lim = problem.JointLimits(-1e6, 1e6, -0.7, 0.9, -1e9, 1e9, -1e12, 1e12)
+    xt = rng.normal(0, 1.5, (10, H))
+    res = admm.admm_joint(xt, H, dt, lim, 0.0, 0.1, iters=3000, tol=1e-12, check_every=10)
+    want = np.clip(xt, -0.7, 0.9)
+    want[:, 0] = 0.1
+    np.testing.assert_allclose(res.x, want, atol=1e-9)
+
+
+def test_feasible_input_returned_unchanged():
+    """A feasible sample with x~_1 = v0 is a fixed point from the first iterate on.
+
+    The oracle's primal step is an LU solve of M, so it returns the input to
+    rounding; the library's incremental form keeps it bit for bit."""
+    H, dt = 20, 0.05
+    lim = problem.joint_limits(W.UR5E_BIMANUAL_BOUNDS(1), 0)
+    t = np.arange(1, H + 1) * dt
+    xt = np.stack([0.3 + 0.2 * np.sin(2 * np.pi * 0.5 * t + p) for p in (0.0, 0.4, 1.0)])
+    xt[:, 0] = 0.3 + 0.2 * np.sin(2 * np.pi * 0.5 * dt + np.array([0.0, 0.4, 1.0]))
+    for c in range(3):
+        v0 = xt[c, 0]
+        rows = problem.velocity_unit_rows(H, dt, lim, 0.0, v0)
+        s = rows.C @ xt[c]
+        assert np.all((s >= rows.lo) & (s <= rows.hi))
+        res = admm.admm_joint(xt[c:c + 1], H, dt, lim, 0.0, v0, iters=100)
+        np.testing.assert_allclose(res.x[0], xt[c], rtol=0, atol=1e-12)
+
+
+def test_primal_step_solves_its_subproblem():
+    """After one iteration x solves min 1/2||x-x~||^2 + rho/2||Cx - z0 + y0/rho||^2, x_1 = v0."""
+    rng = np.random.default_rng(4)
+    H, dt, rho, v0 = 20, 0.05, 1.7, 0.4
+    lim = _lim()
+    rows = problem.velocity_unit_rows(H, dt, lim, 0.05, v0)
+    xt = rng.normal(0, 2, (3, H))
+    x0 = xt.copy()
+    x0[:, 0] = v0
+    z0 = np.clip(x0 @ rows.C.T, rows.lo, rows.hi)
+    res = admm.admm_joint(xt, H, dt, lim, 0.05, v0, rho=rho, iters=1)
+    x1 = res.x
+    grad = (x1 - xt) + rho * (x1 @ rows.C.T - z0) @ rows.C      # y0 = 0
+    np.testing.assert_allclose(grad[:, 1:], 0.0, atol=1e-9)    # row 1 absorbed by mu
+    np.testing.assert_allclose(x1[:, 0], v0, atol=0)
+    # z-step and y-step consistency: z in the box, y sign pattern of the normal cone
+    z, y = res.z, res.y
+    assert np.all(z >= rows.lo - 1e-12) and np.all(z <= rows.hi + 1e-12)
+    interior = (z > rows.lo + 1e-9) & (z < rows.hi - 1e-9)
+    np.testing.assert_allclose(y[interior], 0.0, atol=1e-9)
+    assert np.all(y[np.isclose(z, rows.hi)] >= -1e-12)
+    assert np.all(y[np.isclose(z, rows.lo)] <= 1e-12)
+
+
+def test_dual_residual_identity():
+    """With alpha = 1, r_d equals rho ||C^T (z^L - z^{L-1})|| on rows 2..H."""
+    r = W.config1()
+    j = 3
+    lim = problem.joint_limits(r.bounds, j)
+    rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
+    a = admm.admm_joint(r.samples[:8, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=29)
+    b = admm.admm_joint(r.samples[:8, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=30)
+    direct = np.max(np.abs((b.z - a.z) @ rows.C)[:, 1:], axis=1)
+    np.testing.assert_allclose(b.r_d, direct, rtol=1e-6, atol=1e-9)
+
+
+def test_projection_properties():
+    """Idempotence P(P(x)) = P(x) and non-expansiveness ||P(a)-P(b)|| <= ||a-b||."""
+    rng = np.random.default_rng(9)
+    H, dt = 10, 0.05
+    lim = _lim()
+    q0, v0 = 0.1, 0.2
+    a = rng.normal(0, 2, (6, H))
+    b = a + rng.normal(0, 0.5, (6, H))
+    kw = dict(iters=60000, tol=1e-11, check_every=100, alpha=1.6)
+    pa = admm.admm_joint(a, H, dt, lim, q0, v0, **kw).x
+    pb = admm.admm_joint(b, H, dt, lim, q0, v0, **kw).x
+    ppa = admm.admm_joint(pa, H, dt, lim, q0, v0, **kw).x
+    np.testing.assert_allclose(ppa, pa, atol=1e-8)
+    assert np.all(np.linalg.norm(pa - pb, axis=1) <= np.linalg.norm(a - b, axis=1) + 1e-8)
+
+
+def test_joint_separability_against_stacked_problem():
+    """Per-joint solutions certify as optimal for the stacked eq. (compact_qp) (Sec. III-D)."""
+    r = W.make_request(3, N=2, H=6, nj=3, dt=0.05, kind="white", sigma=2.0)
+    res = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=60000,
+                             tol=1e-11, check_every=100, alpha=1.6)
+    G, h, A, b = problem.stacked_G_h(r.H, r.dt, r.bounds, r.q0, r.v0)
+    for s in range(r.N):
+        xt = r.samples[s].astype(np.float64).reshape(-1)
+        x = res.x[s].reshape(-1)
+        Gx = G @ x
+        assert np.max(Gx - h) < 1e-8
+        act = np.where(Gx >= h - 1e-7)[0]
+        # stationarity: x - xt + G_act^T lam + A^T mu = 0, lam >= 0
+        B = np.hstack([G[act].T, A.T, -A.T])
+        w, _ = scipy.optimize.nnls(B, xt - x)
+        assert np.max(np.abs(B @ w - (xt - x))) < 1e-7
+
+
+def test_grouped_early_exit():
+    r = W.config1()
+    res = admm.solve_request(r.samples[:40], r.H, r.dt, r.bounds, r.q0, r.v0, iters=5000,
+                             tol=1e-3, check_every=10)
+    assert np.all(res.iters % 10 == 0)
+    assert np.all(np.maximum(res.r_p, res.r_d) <= 1e-3)
+    # groups are samples 0-15, 16-31, 32-39 of each joint: one stop count per group
+    for j in range(r.nj):
+        for g0, g1 in ((0, 16), (16, 32), (32, 40)):
+            assert len(set(res.iters[g0:g1, j].tolist())) == 1
+    # fixed-count run with the same count reproduces the early-exit result exactly
+    j = 5
+    n = int(res.iters[0, j])
+    lim = problem.joint_limits(r.bounds, j)
+    fixed = admm.admm_joint(r.samples[:16, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=n)
+    np.testing.assert_array_equal(fixed.x, res.x[:16, :, j])
+
+
+def test_warm_start_at_solution_is_fixed_point():
+    r = W.make_request(2, N=4, H=12, nj=1, dt=0.05, kind="white", sigma=2.0)
+    lim = problem.joint_limits(r.bounds, 0)
+    kw = dict(iters=40000, tol=1e-12, check_every=100)
+    res = admm.admm_joint(r.samples[:, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0], **kw)
+    again = admm.admm_joint(r.samples[:, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0], iters=20,
+                            warm_x=res.x, warm_y=res.y)
+    np.testing.assert_allclose(again.x, res.x, atol=1e-9)
+
+
+def test_literal_iteration_stops_at_any_feasible_point():
+    """As printed, every feasible x paired with lambda = x - x~ is a fixed point, so the
+    iteration settles on a feasible point that need not be x* (documents the reading of
+    the "ADMM Solver" passage; the headline iteration carries y in constraint space)."""
+    rng = np.random.default_rng(12)
+    H, dt = 10, 0.05
+    lim = _lim()
+    q0, v0 = 0.0, 0.2
+    xt = rng.normal(0, 2, (4, H))
+    feasible = np.full((4, H), v0)          # constant velocity: feasible for these limits
+    xl, viol = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=1.0, iters=300,
+                                  x_init=feasible, lam_init=feasible - xt)
+    np.testing.assert_allclose(xl, feasible, atol=1e-9)
+    xstar = admm.admm_joint(xt, H, dt, lim, q0, v0, iters=40000, tol=1e-11, check_every=100).x
+    assert np.max(np.abs(feasible - xstar)) > 0.1
+    # from the sample itself the printed iteration reaches a feasible point, not x*
+    xl2, viol2 = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=1.0, iters=5000)
+    assert np.all(viol2 < 1e-3)
+    assert np.max(np.abs(xl2 - xstar)) > 1e-2
+
+
+def test_kkt_factor_route_equals_reduced_inverse_route():
+    """Iterating with x = K r + k v0 gives the same iterates as the LU solve of M."""
+    r = W.config1()
+    j = 0
+    lim = problem.joint_limits(r.bounds, j)
+    rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
+    K, k = factor.reduced_inverse(factor.penalty_matrix(rows.C, 1.0))
+    xt = r.samples[:5, :, j].astype(np.float64).T
+    x = xt.copy()
+    x[0] = r.v0[j]
+    y = np.zeros((rows.C.shape[0], 5))
+    z = np.clip(rows.C @ x, rows.lo[:, None], rows.hi[:, None])
+    for _ in range(50):
+        x = K @ (xt + rows.C.T @ (z - y)) + k[:, None] * r.v0[j]
+        s = rows.C @ x
+        zn = np.clip(s + y, rows.lo[:, None], rows.hi[:, None])
+        y = y + s - zn
+        z = zn
+    res = admm.admm_joint(r.samples[:5, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=50)
+    np.testing.assert_allclose(res.x, x.T, atol=1e-10)
