@@ -24,8 +24,14 @@ projection. With relaxation alpha (1 = none) one iteration is
     z+  = clip(s^ + y/rho, lo, hi)                                    (Step 1)
     y+  = y + rho (s^ - z+)                                           (Step 3)
 
-started from x0 = x~ with x0_1 := v0, y0 = 0, z0 = clip(C x0) (or a supplied
-warm state (x_w, y_w): x0 = x_w with x0_1 := v0, z0 = clip(C x0 + y_w/rho)).
+Initialization (the paper gives none). Within an iteration the paper takes
+the slack step before the primal step (Step 1 uses the previous iterate x^l),
+so the first pass here is a slack step and a multiplier step from the
+starting point, with the previous slack taken as C x0:
+    x0 = x~ with x0_1 := v0 (or a warm x_w with its first step set to v0),
+    s0 = C x0,   z0 = clip(s0 + y_w/rho),   y0 = y_w + rho (s0 - z0),
+where y_w is a warm multiplier (0 for a cold start). A feasible sample with
+x~_1 = v0 gives z0 = s0 and y0 = 0 and is a fixed point from the start.
 
 Residuals (per column, velocity units, rad/s):
     r_p = max_i |(C x)_i - z_i|                         primal feasibility gap
@@ -92,7 +98,9 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
     x[0, :] = v0
     y = (np.zeros((C.shape[0], ncols)) if warm_y is None
          else np.asarray(warm_y, dtype=np.float64).T.copy())
-    z = np.clip(C @ x + y / rho, lo, hi)
+    s0 = C @ x
+    z = np.clip(s0 + y / rho, lo, hi)
+    y = y + rho * (s0 - z)
 
     done = np.zeros(ncols, dtype=bool)
     n_done = np.full(ncols, iters, dtype=np.int64)

@@ -117,7 +117,8 @@ def test_feasible_input_returned_unchanged():
 
 
 def test_primal_step_solves_its_subproblem():
-    """After one iteration x solves min 1/2||x-x~||^2 + rho/2||Cx - z0 + y0/rho||^2, x_1 = v0."""
+    """After one iteration x solves min 1/2||x-x~||^2 + rho/2||Cx - z0 + y0/rho||^2, x_1 = v0,
+    with z0 = clip(C x0) and y0 = rho (C x0 - z0) from the first slack/multiplier pass."""
     rng = np.random.default_rng(4)
     H, dt, rho, v0 = 20, 0.05, 1.7, 0.4
     lim = _lim()
@@ -125,10 +126,12 @@ def test_primal_step_solves_its_subproblem():
     xt = rng.normal(0, 2, (3, H))
     x0 = xt.copy()
     x0[:, 0] = v0
-    z0 = np.clip(x0 @ rows.C.T, rows.lo, rows.hi)
+    s0 = x0 @ rows.C.T
+    z0 = np.clip(s0, rows.lo, rows.hi)
+    u0 = s0 - z0                                                 # y0 / rho
     res = admm.admm_joint(xt, H, dt, lim, 0.05, v0, rho=rho, iters=1)
     x1 = res.x
-    grad = (x1 - xt) + rho * (x1 @ rows.C.T - z0) @ rows.C      # y0 = 0
+    grad = (x1 - xt) + rho * (x1 @ rows.C.T - z0 + u0) @ rows.C
     np.testing.assert_allclose(grad[:, 1:], 0.0, atol=1e-9)    # row 1 absorbed by mu
     np.testing.assert_allclose(x1[:, 0], v0, atol=0)
     # z-step and y-step consistency: z in the box, y sign pattern of the normal cone
@@ -245,8 +248,9 @@ def test_kkt_factor_route_equals_reduced_inverse_route():
     xt = r.samples[:5, :, j].astype(np.float64).T
     x = xt.copy()
     x[0] = r.v0[j]
-    y = np.zeros((rows.C.shape[0], 5))
-    z = np.clip(rows.C @ x, rows.lo[:, None], rows.hi[:, None])
+    s0 = rows.C @ x
+    z = np.clip(s0, rows.lo[:, None], rows.hi[:, None])
+    y = s0 - z
     for _ in range(50):
         x = K @ (xt + rows.C.T @ (z - y)) + k[:, None] * r.v0[j]
         s = rows.C @ x
