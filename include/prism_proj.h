@@ -1,0 +1,205 @@
+/*
+ * prism_proj.h -- C ABI of the MI355X (gfx950) trajectory-projection library.
+ *
+ * The library projects sampled joint-velocity trajectories onto the set that
+ * satisfies joint position, velocity, acceleration and jerk bounds and the
+ * initial-velocity condition. This is the projection QP of PRISM (arXiv
+ * 2608.25666), Sec. III-A eqs. (proj_cost)-(proj_boundary), in the compact form
+ * of Sec. III-D eq. (compact_qp):
+ *
+ *   x* = argmin 1/2 ||x - x~||^2  s.t.  x_1 = v0,  G x <= h,
+ *
+ * solved independently per (sample, joint) column (Sec. III-D "Joint-wise
+ * separability", "Batch parallelism") with an ADMM splitting whose primal
+ * system is factored once per (H, dt, rho) (Sec. III-D "Pre-computable
+ * factorization") and whose boundary values only change the bounds (Sec. III-D
+ * "Boundary value update").
+ *
+ * Units: rad, rad/s, rad/s^2, rad/s^3; dt in seconds. Residuals are reported
+ * in velocity units (rad/s): every constraint row is scaled by a positive
+ * factor (1, 1/dt, dt, dt^2 for the velocity, position, acceleration and jerk
+ * rows), which leaves the feasible set and the projection unchanged.
+ *
+ * Layouts: trajectories are float32 [N][H][n_joints] row-major (step-major,
+ * joint-minor per sample, as the stacked vector of Sec. III-D eq. (G_h_def)).
+ * Per-column outputs are [N][n_joints].
+ *
+ * Devices and streams: a handle belongs to the HIP device that was current
+ * when it was created; solves must be issued with that device current. Every
+ * solve is asynchronous on the caller's hipStream_t; the caller owns all
+ * sample/output buffers (device memory on the handle's device) and must keep
+ * them alive until the stream reaches the solve. Host arrays (bounds, q0, v0,
+ * request tables) are read before the call returns.
+ *
+ * Errors: every argument check runs before any work is enqueued; on an error
+ * nothing is written to any output. NaN inputs propagate to NaN outputs and NaN
+ * residuals (not checked on the hot path; prism_proj_feasibility reports them).
+ */
+#ifndef PRISM_PROJ_H
+#define PRISM_PROJ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRISM_PROJ_ABI_VERSION 1
+#define PRISM_MAX_H 128          /* horizon limit: the x-update inverse is staged on-chip */
+#define PRISM_MAX_JOINTS 64
+
+typedef struct prism_proj_s* prism_proj_t;   /* opaque, owned by the library */
+
+typedef enum {
+  PRISM_OK = 0,
+  PRISM_EINVAL = -1,        /* bad argument (sizes, bounds, rho, pointers, options) */
+  PRISM_ENOMEM = -2,        /* host or device allocation failed */
+  PRISM_EDEVICE = -3,       /* a HIP call failed, or wrong device current */
+  PRISM_EINFEASIBLE = -4,   /* a necessary boundary condition fails (see solve) */
+  PRISM_EBUSY = -5,         /* server admission refused (budget or queue full) */
+  PRISM_EUNSUPPORTED = -6   /* combination not built into this library */
+} prism_status_t;
+
+/* Joint-wise limits (Sec. III-D "Velocity bounds": joint-wise limit vectors).
+ * Host arrays of length n_joints, copied by prism_proj_create. Each lower
+ * bound must be <= its upper bound and finite. */
+typedef struct {
+  const double *q_min, *q_max;   /* position, rad      */
+  const double *v_min, *v_max;   /* velocity, rad/s    */
+  const double *a_min, *a_max;   /* acceleration       */
+  const double *j_min, *j_max;   /* jerk               */
+} prism_bounds_t;
+
+typedef enum {
+  PRISM_PREC_FP32 = 0,   /* x-update GEMM on FP32 MFMA                              */
+  PRISM_PREC_BF16 = 1,   /* x-update GEMM operands BF16 (RNE), FP32 accumulation    */
+  PRISM_PREC_FP16 = 2    /* x-update GEMM operands FP16 (RNE), FP32 accumulation    */
+} prism_precision_t;
+
+/* Solver options. Everything except the GEMM operands is FP32 (clamps, duals,
+ * stencils, residuals). */
+typedef struct {
+  int32_t precision;    /* prism_precision_t                                         */
+  int32_t fp32_tail;    /* reduced forms: with tol <= 0 the last fp32_tail of the
+                           iterations use the FP32 GEMM; with tol > 0, fp32_tail
+                           FP32 iterations follow convergence                        */
+  float alpha;          /* over-relaxation in (0, 2); 1 = plain ADMM                 */
+  float tol;            /* <= 0: run exactly `iters` iterations. > 0: each group of
+                           16 samples of one joint stops at the first check point
+                           (iteration 0, every check_every iterations, and iters)
+                           where all its columns have max(r_primal, r_dual) <= tol */
+  int32_t check_every;  /* residual check period (>= 1) when tol > 0                 */
+  int32_t reserved[3];  /* must be zero                                              */
+} prism_options_t;
+
+/* Fill *opts with the defaults: FP32, fp32_tail 0, alpha 1, tol 0, check_every 10. */
+void prism_options_default(prism_options_t* opts);
+
+/* prism_proj_create -- build the reusable factor for horizon H and step dt.
+ *
+ * Forms, in FP64 on the host, P = I + rho C^T C for the velocity-unit
+ * constraint rows C = [I; L; D1; D2] (Sec. III-D eqs. (pos_stack), (acc_stack),
+ * (jerk_stack) scaled to rad/s), eliminates the equality x_1 = v0 from the KKT
+ * matrix M of eq. (admm_primal), and keeps K = Pi - Pi e1 e1^T Pi / Pi_11
+ * (Pi = P^-1). C is unit-free after the row scaling, so K depends only on
+ * (H, rho): dt, the bounds, q0 and v0 enter only the row bounds.
+ * FP32/BF16/FP16 copies of K, laid out for the MFMA x-update, are uploaded to
+ * the current device.
+ *
+ * H in [2, PRISM_MAX_H]; n_joints in [1, PRISM_MAX_JOINTS]; dt > 0 finite;
+ * rho > 0 finite; bounds with lo <= hi, all finite.
+ * Returns PRISM_EINVAL on a bad argument, PRISM_ENOMEM / PRISM_EDEVICE on
+ * allocation or HIP failures; *out is written only on PRISM_OK. */
+prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bounds_t* bounds,
+                                 double rho, prism_proj_t* out);
+
+/* Set the handle's default options (used by prism_proj_solve). Not safe to
+ * call while another thread issues solves on the same handle. */
+prism_status_t prism_proj_set_options(prism_proj_t p, const prism_options_t* opts);
+prism_status_t prism_proj_get_options(prism_proj_t p, prism_options_t* opts);
+
+/* prism_proj_solve -- project N sampled trajectories (the hot path).
+ *
+ * v_samples: device, float32 [N][H][n_joints] (x~, the raw samples).
+ * q0, v0:    host, float64 [n_joints] (theta_init, thetadot_init), shared by
+ *            all N samples. They set the first-row bounds (Sec. III-D
+ *            "Boundary value update") and x_1 = v0 (eq. (A_b_def)).
+ * iters:     iteration count (tol <= 0) or cap (tol > 0); >= 0.
+ * v_out:     device, float32 [N][H][n_joints]; may alias v_samples.
+ * r_primal:  device, float32 [N][n_joints]: max_i |(C x)_i - z_i| (rad/s).
+ * r_dual:    device, float32 [N][n_joints]: max over steps k >= 2 of
+ *            |x_k - x~_k + (C^T y)_k| (rad/s), the stationarity gap.
+ * Either residual pointer may be NULL.
+ * Returns PRISM_EINFEASIBLE when v0 is outside [v_min, v_max], q0 + dt*v0
+ * is outside [q_min, q_max], or 0 is outside [a_min, a_max] or [j_min, j_max]
+ * for some joint (the first rows would be unsatisfiable). N = 0 is a no-op. */
+prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N,
+                                const double* q0, const double* v0, int iters, float* v_out,
+                                float* r_primal, float* r_dual, hipStream_t stream);
+
+/* Extended solve: optional per-column iteration counts, warm start and dual
+ * state, and per-call options.
+ *   opts:      NULL = the handle's options.
+ *   iters_out: device int32 [N][n_joints] or NULL: iterations performed.
+ *   x_warm:    device float32 [N][H][n_joints] or NULL: initial iterate
+ *              (its first step is replaced by v0). NULL = start from v_samples.
+ *   u_warm:    device float32 [N][n_joints][4][H] or NULL: initial scaled dual
+ *              u = y / rho per constraint row, blocks velocity, position,
+ *              acceleration, jerk; entry 0 of the jerk block is unused (the
+ *              jerk rows are steps 2..H). NULL = zero.
+ *   u_out:     device float32 [N][n_joints][4][H] or NULL: final scaled dual in
+ *              the same layout (for warm-starting the next MPC step).
+ * With x_warm / u_warm the start is z0 = clip(C x0 + u0) (cold start: u0 = 0). */
+typedef struct {
+  const float* v_samples;
+  int32_t N;
+  int32_t iters;
+  const double* q0;
+  const double* v0;
+  float* v_out;
+  float* r_primal;
+  float* r_dual;
+  int32_t* iters_out;
+  const float* x_warm;
+  const float* u_warm;
+  float* u_out;
+  const prism_options_t* opts;
+} prism_solve_args_t;
+
+prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* args,
+                                   hipStream_t stream);
+
+/* prism_proj_feasibility -- FP64 final check of trajectories (device kernel).
+ * For each column writes to viol (device, float64 [N][n_joints][5]) the largest
+ * violation of the position (rad), velocity (rad/s), acceleration (rad/s^2)
+ * and jerk (rad/s^3) bounds, and |x_1 - v0|, recomputing positions by forward
+ * Euler and derivatives by backward differences in FP64 (Sec. III-D
+ * "From Joint-Velocity Sequences to Derivative Bounds"). NaN input gives NaN. */
+prism_status_t prism_proj_feasibility(prism_proj_t p, const float* v, int N, const double* q0,
+                                      const double* v0, double* viol, hipStream_t stream);
+
+/* Release the handle and its device memory. The caller must ensure no solve
+ * that uses it is still pending on any stream. NULL is ignored. */
+void prism_proj_destroy(prism_proj_t p);
+
+/* Introspection for tests and tools. */
+int prism_proj_horizon(prism_proj_t p);
+int prism_proj_joints(prism_proj_t p);
+
+/* Copy the FP64 reduced inverse K (H*H, row-major) and k (H) built by create
+ * into host arrays. Host-only; usable without a GPU via prism_factor_host. */
+prism_status_t prism_proj_get_factor(prism_proj_t p, double* K, double* k);
+
+/* Host-only factor build (no device work), same arithmetic as create:
+ * K (H*H row-major) and k (H). Returns PRISM_EINVAL on bad arguments. */
+prism_status_t prism_factor_host(int H, double rho, double* K, double* k);
+
+const char* prism_status_str(prism_status_t s);
+int prism_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRISM_PROJ_H */

@@ -1,0 +1,108 @@
+"""ctypes declarations of the C ABI in include/prism_proj.h.
+
+Loading fails loudly when libprism_proj.so has not been built: there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libprism_proj.so")
+
+PRISM_OK = 0
+PRISM_EINVAL = -1
+PRISM_ENOMEM = -2
+PRISM_EDEVICE = -3
+PRISM_EINFEASIBLE = -4
+PRISM_EBUSY = -5
+PRISM_EUNSUPPORTED = -6
+
+PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+MAX_H = 128
+MAX_JOINTS = 64
+
+
+class PrismError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.prism_status_str(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+class Bounds(C.Structure):
+    _fields_ = [(n, C.POINTER(C.c_double)) for n in
+                ("q_min", "q_max", "v_min", "v_max", "a_min", "a_max", "j_min", "j_max")]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("fp32_tail", C.c_int32), ("alpha", C.c_float),
+                ("tol", C.c_float), ("check_every", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class SolveArgs(C.Structure):
+    _fields_ = [("v_samples", C.c_void_p), ("N", C.c_int32), ("iters", C.c_int32),
+                ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
+                ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
+                ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("u_warm", C.c_void_p),
+                ("u_out", C.c_void_p), ("opts", C.POINTER(Options))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2608_25666_amd.build or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    H = C.c_void_p      # opaque handle
+    st = C.c_int
+    sig = {
+        "prism_options_default": (None, [C.POINTER(Options)]),
+        "prism_proj_create": (st, [C.c_int, C.c_int, C.c_double, C.POINTER(Bounds), C.c_double,
+                                   C.POINTER(H)]),
+        "prism_proj_set_options": (st, [H, C.POINTER(Options)]),
+        "prism_proj_get_options": (st, [H, C.POINTER(Options)]),
+        "prism_proj_solve": (st, [H, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.c_int, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]),
+        "prism_proj_solve_ex": (st, [H, C.POINTER(SolveArgs), C.c_void_p]),
+        "prism_proj_feasibility": (st, [H, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+        "prism_proj_destroy": (None, [H]),
+        "prism_proj_horizon": (C.c_int, [H]),
+        "prism_proj_joints": (C.c_int, [H]),
+        "prism_proj_get_factor": (st, [H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "prism_factor_host": (st, [C.c_int, C.c_double, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
+        "prism_status_str": (C.c_char_p, [C.c_int]),
+        "prism_abi_version": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def lib():
+    return load()
+
+
+def check(status: int, where: str):
+    if status != PRISM_OK:
+        raise PrismError(status, where)
+
+
+def dbl_array(values):
+    arr = (C.c_double * len(values))(*[float(v) for v in values])
+    return arr

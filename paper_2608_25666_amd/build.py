@@ -1,0 +1,102 @@
+"""Build libprism_proj.so (HIP for gfx950) in-tree.
+
+    python -m paper_2608_25666_amd.build [--jobs N] [--incremental]
+
+Every HIP/C++ source under csrc/ is compiled with hipcc for gfx950 (objects in
+_build/ at the repository root) and linked into paper_2608_25666_amd/libprism_proj.so.
+Packed FP32 instructions are disabled for all device code.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import glob
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(ROOT, "_build", "obj")
+LIB = os.path.join(PKG, "libprism_proj.so")
+ARCH = "gfx950"
+
+COMMON = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", INCLUDE, "-I", CSRC,
+]
+
+
+def hipcc() -> str:
+    for cand in ("/opt/rocm/bin/hipcc", shutil.which("hipcc") or ""):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build the HIP library)")
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def _newest_header() -> float:
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return max(os.path.getmtime(h) for h in hs) if hs else 0.0
+
+
+def _compile(src: str, incremental: bool, hdr_time: float):
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        ot = os.path.getmtime(obj)
+        if ot > os.path.getmtime(src) and ot > hdr_time:
+            return obj, 0.0, ""
+    cmd = [hipcc()] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
+    t0 = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{err}")
+    return obj, time.time() - t0, err
+
+
+def build(jobs: int = 0, incremental: bool = False, verbose: bool = False) -> str:
+    """Compile every source and link the shared library; returns its path."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or max(1, min(16, os.cpu_count() or 4))
+    hdr_time = _newest_header()
+    srcs = sources()
+    objs = []
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = {ex.submit(_compile, s, incremental, hdr_time): s for s in srcs}
+        for f in cf.as_completed(futs):
+            obj, dt, err = f.result()
+            objs.append(obj)
+            if verbose:
+                print(f"  {os.path.basename(futs[f]):24s} {dt:6.1f} s", flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + sorted(objs)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} in {time.time() - t0:.1f} s", flush=True)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--jobs", type=int, default=0)
+    ap.add_argument("--incremental", action="store_true")
+    a = ap.parse_args(argv)
+    build(jobs=a.jobs, incremental=a.incremental, verbose=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

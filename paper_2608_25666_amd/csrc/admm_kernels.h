@@ -1,0 +1,50 @@
+// Persistent ADMM kernels: a workgroup of up to eight waves stages the permuted
+// inverse K in LDS once, then each wave pulls tiles (16 samples of one joint)
+// from a global counter until none are left. HBM is touched only to load the
+// samples and store the projected trajectories and residuals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "admm_tile.h"
+#include "kernel_args.h"
+
+namespace prism {
+
+template <int HQ, bool EXACT, int GEMM>
+__global__ __launch_bounds__(256) void admm_solve_kernel(SolveKernelArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  {
+    // stage FP32 fragments, then the 16-bit fragments of the reduced forms
+    const int nbytes = A.frag_f32_bytes + (GEMM == GEMM_F32 ? 0 : A.frag_16_bytes);
+    const v4u* src = reinterpret_cast<const v4u*>(A.frag);
+    v4u* dst = reinterpret_cast<v4u*>(lds);
+    for (int i = threadIdx.x; i < nbytes / 16; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const float* kf32 = reinterpret_cast<const float*>(lds);
+  const void* k16 = lds + A.frag_f32_bytes;
+  const int frag_bytes = A.frag_f32_bytes + (GEMM == GEMM_F32 ? 0 : A.frag_16_bytes);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  float* xt_wave = reinterpret_cast<float*>(lds + frag_bytes) + wave * (HQ * 64);
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(A.counter, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= A.ntiles) break;
+    const int j = t % A.nj;
+    const int sb = t / A.nj;
+    TileSolver<HQ, EXACT, GEMM> ts;
+    ts.run(A, j, sb * kTileCols, kf32, k16, xt_wave);
+  }
+}
+
+using SolveKernelFn = void (*)(SolveKernelArgs);
+
+// Kernel for chunk size HQ (2..32), exact fit (4*HQ == H) and GEMM precision.
+SolveKernelFn solve_kernel_f32(int HQ, bool exact);
+SolveKernelFn solve_kernel_bf16(int HQ, bool exact);
+SolveKernelFn solve_kernel_f16(int HQ, bool exact);
+
+}  // namespace prism

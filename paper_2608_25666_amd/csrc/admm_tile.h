@@ -1,0 +1,492 @@
+// Fused ADMM tile solver for gfx950 (CDNA4), device code.
+//
+// One wavefront projects a tile of 16 columns: samples s0..s0+15 of one joint
+// (Sec. III-D "Joint-wise separability": every (sample, joint) column is an
+// independent H-step QP with the same matrices). Lane l = 16*g + c owns column
+// c and the HQ consecutive steps g*HQ .. g*HQ+HQ-1 ("chunk g"). This is the
+// accumulator layout of v_mfma_f32_16x16x4_f32 once the shared inverse K has
+// its rows and columns permuted on the host, so the x-update x += K d
+// (Sec. III-D "Step 2: Primal update", in incremental form) runs on MFMA with
+// both operands coming straight from registers, while the row stencils run on
+// the VALU with only a handful of cross-lane reads per iteration.
+//
+// ADMM state per column, all FP32 in registers:
+//   x  (H)       primal iterate (MFMA accumulator),
+//   x~ (H)       the sample (kept in LDS, read once per iteration),
+//   q  (4 x H)   q = (1 - alpha) z + u per constraint row (u = y / rho),
+//   sw (H)       C^T w, then the defect d = (x~ - x) + rho C^T w.
+// Constraint rows per step k (velocity units, see JointRowParams):
+//   V: x_k   Q: sum_{i<=k} x_i   A: x_k - x_{k-1}   J: A_k - A_{k-1}.
+// One iteration (rows updated with the current s = C x):
+//   t = alpha s + q,  z = clip(t, lb, ub),  q' = t - alpha z,
+//   w = 2 z - t - s  (= z - s - u'),  d = (x~ - x) + rho C^T w,  x += K d.
+// This is the scaled ADMM of the paper's splitting (slack clip = Step 1,
+// primal solve = Step 2, multiplier update = Step 3, multiplier carried in the
+// constraint space), written with one state per row and an incremental
+// primal step so that reduced-precision GEMM operands only round the defect.
+//
+// Residuals (check iterations): e = z - s per row,
+//   r_p = max |e|,  r_d = max_{step >= 2} |rho C^T e - d|,
+// which equals |x - x~ + rho C^T u| (the stationarity gap) in exact arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kernel_args.h"
+
+namespace prism {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float lane_read(float v, int src_byte_addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte_addr, __float_as_int(v)));
+}
+
+__device__ __forceinline__ float med3(float t, float lo, float hi) {
+  return __builtin_amdgcn_fmed3f(t, lo, hi);
+}
+
+// Hide a value from loop-invariant code motion and CSE. Per-row addresses are
+// cheap to recompute but, if hoisted out of the iteration loop, each one would
+// occupy registers for the whole solve.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+
+// Write-only target for stores of lanes whose row or column lies outside the
+// problem (padding rows of the last chunk, samples past N). Redirecting those
+// stores keeps every store unconditional, so the solver has no divergent
+// branches. Large enough for any per-lane row offset (4 blocks x PRISM_MAX_H).
+static __device__ float g_store_sink[4 * 128 + 64];
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int HQ, bool EXACT, int GEMM>
+struct TileSolver {
+  static constexpr int NB = (HQ + 3) / 4;    // 16-row output blocks (4 registers each)
+  static constexpr int NJ4 = (HQ + 3) / 4;   // FP32 k-steps, grouped by four
+  static constexpr int NJ8 = (HQ + 7) / 8;   // 16-bit k-steps of eight
+
+  v4f xb[NB];
+  float* xt_lds;     // this wave's copy of the samples in LDS, [HQ][64]
+  float qv[HQ], qq[HQ], qa[HQ], qj[HQ];
+  float sw[HQ];
+  float se[HQ];
+  float offw, offe;
+  float rpm, rdm;
+
+  int lane, g, nvalid;
+  int a_prev, a_next, a_prev2, a_next2;   // ds_bpermute byte addresses
+  float lbV, ubV, lbQ, ubQ, lbA, ubA, lbJ, ubJ, v0;
+  float rho, alpha, oma;
+
+  __device__ __forceinline__ float X(int i) const { return xb[i >> 2][i & 3]; }
+
+  // Rows past the horizon (only in the last chunk(s)) must not feed back.
+  __device__ __forceinline__ bool row_ok(int i) const {
+    if (EXACT || i < HQ - 3) return true;
+    return i < nvalid;
+  }
+  __device__ __forceinline__ float mask(int i, float v) const {
+    if (EXACT || i < HQ - 3) return v;
+    return i < nvalid ? v : 0.0f;
+  }
+
+  __device__ __forceinline__ float excl_prefix(float T) const {   // sum over lower chunks
+    float a = lane_read(T, a_prev);
+    a = (g == 0) ? 0.0f : a;
+    const float p2 = T + a;
+    float b = lane_read(p2, a_prev2);
+    b = (g < 2) ? 0.0f : b;
+    return a + b;
+  }
+  __device__ __forceinline__ float excl_suffix(float T) const {   // sum over higher chunks
+    float a = lane_read(T, a_next);
+    a = (g == 3) ? 0.0f : a;
+    const float p2 = T + a;
+    float b = lane_read(p2, a_next2);
+    b = (g >= 2) ? 0.0f : b;
+    return a + b;
+  }
+
+  // One constraint row: slack clip and multiplier update from s = (C x)_row.
+  template <bool CHECK>
+  __device__ __forceinline__ float rowop(float s, float& q, float lb, float ub, float& e,
+                                         float& u) const {
+    const float t = fmaf(alpha, s, q);
+    const float z = med3(t, lb, ub);
+    q = fmaf(-alpha, z, t);
+    const float w = fmaf(2.0f, z, -t) - s;
+    if constexpr (CHECK) { e = z - s; u = t - z; }
+    return w;
+  }
+
+  // Row update for every block and transposed accumulation sw = C^T w
+  // (se = C^T e on check iterations). uo: where to store u (check only).
+  template <bool CHECK>
+  __device__ __forceinline__ void row_update(float* __restrict__ uo, int H) {
+    float e = 0.0f, u = 0.0f;
+    float* upb[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool store_u = CHECK && (uo != nullptr);   // wave-uniform
+    if constexpr (CHECK) {
+      rpm = 0.0f;
+      if (store_u) {
+        // one base per block so that every row store uses an immediate offset
+#pragma unroll
+        for (int b = 0; b < 4; ++b) upb[b] = opaque(uo + b * H + g * HQ);
+      }
+    }
+    auto track = [&](int i, float ev, float uv, int blk) {
+      if constexpr (CHECK) {
+        rpm = fmaxf(rpm, fabsf(ev));
+        if (store_u) {
+          float* dst = upb[blk] + i;
+          if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
+          *dst = uv;
+        }
+      }
+    };
+    // ---- position block: s = prefix sum (chunk prefix + lower chunks' totals)
+    {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) { acc += X(i); sw[i] = acc; }
+      const float off = excl_prefix(acc);
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        const float s = sw[i] + off;
+        float w = rowop<CHECK>(s, qq[i], lbQ, ubQ, e, u);
+        w = mask(i, w);
+        sw[i] = w;
+        if constexpr (CHECK) { e = mask(i, e); se[i] = e; track(i, e, u, 1); }
+      }
+      // C_Q^T: suffix sums within the chunk, higher chunks' totals added to d later
+      float suf = 0.0f, sufe = 0.0f;
+#pragma unroll
+      for (int i = HQ - 1; i >= 0; --i) {
+        suf += sw[i];
+        sw[i] = suf;
+        if constexpr (CHECK) { sufe += se[i]; se[i] = sufe; }
+      }
+      offw = excl_suffix(suf);
+      if constexpr (CHECK) offe = excl_suffix(sufe);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- velocity block: s = x
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) {
+      float w = rowop<CHECK>(X(i), qv[i], lbV, ubV, e, u);
+      sw[i] += mask(i, w);
+      if constexpr (CHECK) { e = mask(i, e); se[i] += e; track(i, e, u, 0); }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- acceleration and jerk blocks, streamed along the chunk.
+    // C_A^T w_A + C_J^T w_J = D^T v with v_k = wA_k + wJ_k - wJ_{k+1}, (D^T v)_k = v_k - v_{k+1}.
+    {
+      const float xl = X(HQ - 1);
+      const float al = X(HQ - 1) - X(HQ - 2);
+      float xprev = lane_read(xl, a_prev);
+      float aprev = lane_read(al, a_prev);
+      xprev = (g == 0) ? v0 : xprev;
+      aprev = (g == 0) ? 0.0f : aprev;
+      float wa_p = 0.0f, wj_p = 0.0f, wj_0 = 0.0f, v_0 = 0.0f, v_pm = 0.0f;
+      float ea_p = 0.0f, ej_p = 0.0f, ej_0 = 0.0f, ve_0 = 0.0f, ve_pm = 0.0f;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        const float sa = X(i) - xprev;
+        const float sj = sa - aprev;
+        xprev = X(i);
+        aprev = sa;
+        float ea = 0.0f, ej = 0.0f, ua = 0.0f, uj = 0.0f;
+        float wa = mask(i, rowop<CHECK>(sa, qa[i], lbA, ubA, ea, ua));
+        float wj = mask(i, rowop<CHECK>(sj, qj[i], lbJ, ubJ, ej, uj));
+        if constexpr (CHECK) {
+          ea = mask(i, ea);
+          ej = mask(i, ej);
+          track(i, ea, ua, 2);
+          track(i, ej, uj, 3);
+        }
+        if (i == 0) {
+          wj_0 = wj;
+          if constexpr (CHECK) ej_0 = ej;
+        } else {
+          const float v = wa_p + wj_p - wj;
+          float ve = 0.0f;
+          if constexpr (CHECK) ve = ea_p + ej_p - ej;
+          if (i == 1) {
+            v_0 = v;
+            if constexpr (CHECK) ve_0 = ve;
+          } else {
+            sw[i - 2] += v_pm - v;
+            if constexpr (CHECK) se[i - 2] += ve_pm - ve;
+          }
+          v_pm = v;
+          if constexpr (CHECK) ve_pm = ve;
+        }
+        wa_p = wa;
+        wj_p = wj;
+        if constexpr (CHECK) { ea_p = ea; ej_p = ej; }
+      }
+      float wj_n = lane_read(wj_0, a_next);
+      wj_n = (g == 3) ? 0.0f : wj_n;
+      const float v_last = wa_p + wj_p - wj_n;
+      sw[HQ - 2] += v_pm - v_last;
+      float v_n = lane_read(v_0, a_next);
+      v_n = (g == 3) ? 0.0f : v_n;
+      sw[HQ - 1] += v_last - v_n;
+      if constexpr (CHECK) {
+        float ej_n = lane_read(ej_0, a_next);
+        ej_n = (g == 3) ? 0.0f : ej_n;
+        const float ve_last = ea_p + ej_p - ej_n;
+        se[HQ - 2] += ve_pm - ve_last;
+        float ve_n = lane_read(ve_0, a_next);
+        ve_n = (g == 3) ? 0.0f : ve_n;
+        se[HQ - 1] += ve_last - ve_n;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- defect d = (x~ - x) + rho C^T w; dual residual on check iterations
+    if constexpr (CHECK) rdm = 0.0f;
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) {
+      const float d = fmaf(rho, sw[i] + offw, xt_lds[i * 64 + lane] - X(i));
+      sw[i] = d;
+      if constexpr (CHECK) {
+        float r = fabsf(fmaf(rho, se[i] + offe, -d));
+        r = mask(i, r);
+        if (i == 0) r = (g == 0) ? 0.0f : r;     // step 1: absorbed by x_1 = v0
+        rdm = fmaxf(rdm, r);
+      }
+    }
+  }
+
+  // x += K d with FP32 operands (v_mfma_f32_16x16x4_f32). Fragments stream
+  // from LDS one float4 ahead; the barriers keep the scheduler from hoisting
+  // the whole of K into registers.
+  __device__ __forceinline__ void gemm_f32(const float* __restrict__ kf) {
+    __asm__ volatile("" ::: "memory");
+    const v4f* k4 = reinterpret_cast<const v4f*>(kf) + lane;
+    v4f a = k4[0];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int jj = 0; jj < NJ4; ++jj) {
+        const int idx = b * NJ4 + jj;
+        v4f an = a;
+        if (idx + 1 < NB * NJ4) an = k4[(idx + 1) * 64];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 4 * jj + e;
+          if (j < HQ) xb[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], sw[j], xb[b], 0, 0, 0);
+        }
+        a = an;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+
+  // x += K d with 16-bit operands and FP32 accumulation (v_mfma_f32_16x16x32_*).
+  __device__ __forceinline__ void gemm_16(const void* __restrict__ kl) {
+    __asm__ volatile("" ::: "memory");
+    const v4u* k16 = reinterpret_cast<const v4u*>(kl) + lane;
+    using VT = typename std::conditional<GEMM == GEMM_BF16, v8bf, v8h>::type;
+    using ST = typename std::conditional<GEMM == GEMM_BF16, __bf16, _Float16>::type;
+    VT dv[NJ8];
+#pragma unroll
+    for (int jj = 0; jj < NJ8; ++jj)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 8 * jj + e;
+        dv[jj][e] = (j < HQ) ? (ST)sw[j] : (ST)0.0f;
+      }
+    v4u a = k16[0];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int jj = 0; jj < NJ8; ++jj) {
+        const int idx = b * NJ8 + jj;
+        v4u an = a;
+        if (idx + 1 < NB * NJ8) an = k16[(idx + 1) * 64];
+        if constexpr (GEMM == GEMM_BF16)
+          xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), dv[jj], xb[b], 0, 0, 0);
+        else
+          xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), dv[jj], xb[b], 0, 0, 0);
+        a = an;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+
+  // q <- (1 - alpha) C x + q for every row (first pass with alpha != 1).
+  __device__ __forceinline__ void prep_q() {
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) { acc += X(i); sw[i] = acc; }
+    const float off = excl_prefix(acc);
+    float xprev = lane_read(X(HQ - 1), a_prev);
+    float aprev = lane_read(X(HQ - 1) - X(HQ - 2), a_prev);
+    xprev = (g == 0) ? v0 : xprev;
+    aprev = (g == 0) ? 0.0f : aprev;
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) {
+      const float sa = X(i) - xprev;
+      const float sj = sa - aprev;
+      xprev = X(i);
+      aprev = sa;
+      qv[i] = fmaf(oma, X(i), qv[i]);
+      qq[i] = fmaf(oma, sw[i] + off, qq[i]);
+      qa[i] = fmaf(oma, sa, qa[i]);
+      qj[i] = fmaf(oma, sj, qj[i]);
+    }
+  }
+
+  __device__ void run(const SolveKernelArgs& A, int j, int s0, const float* __restrict__ kf32,
+                      const void* __restrict__ k16, float* xt_wave) {
+    xt_lds = xt_wave;
+    lane = threadIdx.x & 63;
+    g = lane >> 4;
+    const int c = lane & 15;
+    a_prev = ((lane - 16) & 63) << 2;
+    a_next = ((lane + 16) & 63) << 2;
+    a_prev2 = ((lane - 32) & 63) << 2;
+    a_next2 = ((lane + 32) & 63) << 2;
+    const int H = A.H, nj = A.nj;
+    const int s = s0 + c;
+    const bool col_ok = s < A.N;
+    const int s_ld = col_ok ? s : A.N - 1;     // loads always read a valid column
+    {
+      const int nv = H - g * HQ;
+      nvalid = nv < 0 ? 0 : (nv > HQ ? HQ : nv);
+    }
+    const JointRowParams& jp = A.jp[j];
+    lbV = jp.lb[0]; ubV = jp.ub[0];
+    lbQ = jp.lb[1]; ubQ = jp.ub[1];
+    lbA = jp.lb[2]; ubA = jp.ub[2];
+    lbJ = jp.lb[3]; ubJ = jp.ub[3];
+    v0 = jp.v0;
+    rho = A.rho;
+    alpha = A.alpha;
+    oma = 1.0f - A.alpha;
+
+    // ---- load the sample (and warm state). Lane bases include the chunk
+    // offset so the per-row offsets i*nj are wave-uniform; rows past H read
+    // row 0 of the column and are zeroed.
+    const size_t colbase = (size_t)s_ld * H * nj + j;
+    const size_t chunk = (size_t)(g * HQ) * nj;
+    auto ld_row = [&](const float* p, int i) -> float {
+      if (EXACT || i < HQ - 3) return p[i * nj];
+      const int r = (i < nvalid) ? i : -g * HQ;  // row 0 of this column
+      const float v = p[r * nj];
+      return (i < nvalid) ? v : 0.0f;
+    };
+    {
+      const float* px = opaque(A.xin + colbase + chunk);
+#pragma unroll
+      for (int i = 0; i < 4 * NB; ++i) {
+        const float v = (i < HQ) ? ld_row(px, i) : 0.0f;
+        xb[i >> 2][i & 3] = v;
+        if (i < HQ) xt_lds[i * 64 + lane] = v;
+      }
+    }
+    if (A.xw != nullptr) {
+      const float* pw = opaque(A.xw + colbase + chunk);
+#pragma unroll
+      for (int i = 0; i < 4 * NB; ++i) xb[i >> 2][i & 3] = (i < HQ) ? ld_row(pw, i) : 0.0f;
+    }
+    if (g == 0) xb[0][0] = v0;                 // x_1 = v0 (eq. (A_b_def))
+    const size_t ubase = ((size_t)s_ld * nj + j) * 4 * H;
+    if (A.uw != nullptr) {
+      const float* pu = opaque(A.uw + ubase + g * HQ);
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        const int r = (EXACT || i < HQ - 3 || i < nvalid) ? i : -g * HQ;
+        const bool ok = EXACT || i < HQ - 3 || i < nvalid;
+        qv[i] = ok ? pu[0 * H + r] : 0.0f;
+        qq[i] = ok ? pu[1 * H + r] : 0.0f;
+        qa[i] = ok ? pu[2 * H + r] : 0.0f;
+        qj[i] = ok ? pu[3 * H + r] : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) { qv[i] = 0.0f; qq[i] = 0.0f; qa[i] = 0.0f; qj[i] = 0.0f; }
+    }
+    if (g == 0) { qa[0] = 0.0f; qj[0] = 0.0f; }   // rows fixed by x_1 = v0 carry no dual
+    // per-lane u output base: columns past N write to the sink
+    float* uo = nullptr;
+    if (A.uout != nullptr) uo = col_ok ? A.uout + ubase : g_store_sink;
+
+    // The first pass takes the slack and multiplier steps from x0 with the
+    // previous slack set to C x0: q = (1 - alpha) C x0 + u0, so every pass,
+    // including this one, is the same row update.
+    if (A.alpha != 1.0f) prep_q();
+
+    const bool tolmode = A.tolmode != 0;
+    const bool reduced = GEMM != GEMM_F32;
+    const int iters = A.iters;
+    const int ce = A.check_every;
+    const int f32_from = (!reduced || tolmode) ? 0 : iters - A.tail;
+    int it = 0;
+    int tail_left = -1;          // >= 0 while running FP32 iterations after convergence
+    for (;;) {
+      const bool chk = (it == iters) || (tolmode && (it % ce) == 0) || tail_left == 0;
+      if (chk) row_update<true>(uo, H);
+      else row_update<false>(uo, H);
+      if (tail_left == 0) break;
+      if (chk && tolmode && tail_left < 0) {
+        const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
+        if (wave_max(r) <= A.tol) {
+          if (!reduced || A.tail <= 0) break;
+          tail_left = A.tail;
+        }
+      }
+      if (it == iters && tail_left < 0) break;
+      if (!reduced || it >= f32_from || tail_left > 0) gemm_f32(kf32);
+      else gemm_16(k16);
+      ++it;
+      if (tail_left > 0) --tail_left;
+    }
+
+    // ---- store x and the per-column residuals
+    bool bad = false;
+    {
+      float* po = opaque(col_ok ? A.xout + colbase + chunk : g_store_sink);
+      const int st = col_ok ? nj : 0;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        const float v = X(i);
+        bad |= (v != v);
+        float* dst = po + i * st;
+        if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
+        *dst = v;
+      }
+    }
+    float rp = rpm, rd = rdm;
+    rp = fmaxf(rp, __shfl_xor(rp, 16, 64));
+    rp = fmaxf(rp, __shfl_xor(rp, 32, 64));
+    rd = fmaxf(rd, __shfl_xor(rd, 16, 64));
+    rd = fmaxf(rd, __shfl_xor(rd, 32, 64));
+    int anybad = bad ? 1 : 0;
+    anybad |= __shfl_xor(anybad, 16, 64);
+    anybad |= __shfl_xor(anybad, 32, 64);
+    if (anybad) { rp = __builtin_nanf(""); rd = __builtin_nanf(""); }
+    if (g == 0 && col_ok) {
+      const size_t o = (size_t)s * nj + j;
+      if (A.rp) A.rp[o] = rp;
+      if (A.rd) A.rd[o] = rd;
+      if (A.itout) A.itout[o] = it;
+    }
+  }
+};
+
+}  // namespace prism

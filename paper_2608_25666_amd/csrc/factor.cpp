@@ -1,0 +1,165 @@
+// FP64 host construction of the reusable x-update factor.
+//
+// Sec. III-D, "Step 2: Primal update" (eqs. (admm_primal), (admm_KKT)) solves
+//   [P  e1][x ]   [r ]
+//   [e1' 0][mu] = [v0],   P = I + rho C^T C,
+// and "Pre-computable factorization" factors it once. Eliminating mu gives
+//   x = K r + k v0,  K = Pi - Pi e1 e1' Pi / Pi_11,  k = Pi e1 / Pi_11,  Pi = P^-1.
+// C = [I; L; D1; D2] are the constraint rows after scaling every block to
+// velocity units (cumulative sum L, first difference D1, second difference D2
+// of Sec. III-D eqs. (pos_stack), (acc_stack), (D2_def)), so K depends on H and
+// rho only. K is symmetric, K e1 = 0 (the fixed first step never moves) and
+// K P = I - k e1'.
+#include "factor.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace prism {
+
+namespace {
+
+// G = C^T C for C = [I; L; D1; D2], assembled from the row definitions.
+void gram(int H, std::vector<double>& G) {
+  G.assign((size_t)H * H, 0.0);
+  auto add_row = [&](const std::vector<std::pair<int, double>>& row) {
+    for (auto& a : row)
+      for (auto& b : row) G[(size_t)a.first * H + b.first] += a.second * b.second;
+  };
+  for (int i = 0; i < H; ++i) add_row({{i, 1.0}});                       // velocity rows
+  for (int i = 0; i < H; ++i) {                                           // position rows
+    std::vector<std::pair<int, double>> row;
+    for (int c = 0; c <= i; ++c) row.push_back({c, 1.0});
+    add_row(row);
+  }
+  for (int i = 0; i < H; ++i) {                                           // acceleration rows
+    if (i == 0) add_row({{0, 1.0}});
+    else add_row({{i, 1.0}, {i - 1, -1.0}});
+  }
+  for (int r = 0; r + 1 < H; ++r) {                                       // jerk rows, steps 2..H
+    if (r == 0) add_row({{0, -2.0}, {1, 1.0}});
+    else add_row({{r - 1, 1.0}, {r, -2.0}, {r + 1, 1.0}});
+  }
+}
+
+// In-place Cholesky A = R R^T (lower R); returns false if not positive definite.
+bool cholesky(int n, std::vector<double>& A) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    const double rjj = std::sqrt(d);
+    A[(size_t)j * n + j] = rjj;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = s / rjj;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+bool build_factor(int H, double rho, std::vector<double>& K, std::vector<double>& k) {
+  std::vector<double> P;
+  gram(H, P);
+  for (auto& v : P) v *= rho;
+  for (int i = 0; i < H; ++i) P[(size_t)i * H + i] += 1.0;
+  std::vector<double> R = P;
+  if (!cholesky(H, R)) return false;
+  // Pi = P^-1 column by column: solve R y = e_c, R^T x = y.
+  std::vector<double> Pi((size_t)H * H, 0.0), y(H), x(H);
+  for (int c = 0; c < H; ++c) {
+    for (int i = 0; i < H; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int t = 0; t < i; ++t) s -= R[(size_t)i * H + t] * y[t];
+      y[i] = s / R[(size_t)i * H + i];
+    }
+    for (int i = H - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int t = i + 1; t < H; ++t) s -= R[(size_t)t * H + i] * x[t];
+      x[i] = s / R[(size_t)i * H + i];
+    }
+    for (int i = 0; i < H; ++i) Pi[(size_t)i * H + c] = x[i];
+  }
+  // symmetrize (the two triangular solves leave rounding asymmetry)
+  for (int i = 0; i < H; ++i)
+    for (int j = i + 1; j < H; ++j) {
+      const double m = 0.5 * (Pi[(size_t)i * H + j] + Pi[(size_t)j * H + i]);
+      Pi[(size_t)i * H + j] = Pi[(size_t)j * H + i] = m;
+    }
+  const double p11 = Pi[0];
+  K.assign((size_t)H * H, 0.0);
+  k.assign(H, 0.0);
+  for (int i = 0; i < H; ++i) k[i] = Pi[(size_t)i * H] / p11;
+  for (int i = 1; i < H; ++i)
+    for (int j = 1; j < H; ++j)
+      K[(size_t)i * H + j] = Pi[(size_t)i * H + j] - Pi[(size_t)i * H] * Pi[(size_t)j * H] / p11;
+  // row and column 0 are exactly zero: the first step is pinned to v0
+  return true;
+}
+
+namespace {
+
+// Physical step held by A-operand row m of output block b (see the kernel's
+// register layout): lane group m/4 of the output, chunk register 4b + m%4.
+inline int out_row(int b, int m, int HQ, int H) {
+  const int reg = 4 * b + (m & 3);
+  const int row = (m >> 2) * HQ + reg;
+  return (reg < HQ && row < H) ? row : -1;
+}
+
+inline int in_row(int gk, int j, int HQ, int H) {
+  const int row = gk * HQ + j;
+  return (j < HQ && row < H) ? row : -1;
+}
+
+}  // namespace
+
+void layout_f32(const std::vector<double>& K, int H, int HQ, std::vector<float>& out) {
+  const int nb = (HQ + 3) / 4, nj4 = (HQ + 3) / 4;
+  out.assign((size_t)nb * nj4 * 64 * 4, 0.0f);
+  for (int b = 0; b < nb; ++b)
+    for (int jj = 0; jj < nj4; ++jj)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 4; ++e) {
+          const int r = out_row(b, lane & 15, HQ, H);
+          const int c = in_row(lane >> 4, 4 * jj + e, HQ, H);
+          const float v = (r >= 0 && c >= 0) ? (float)K[(size_t)r * H + c] : 0.0f;
+          out[(((size_t)b * nj4 + jj) * 64 + lane) * 4 + e] = v;
+        }
+}
+
+uint16_t float_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t float_to_f16_rne(float f) {
+  _Float16 h = (_Float16)f;   // IEEE round-to-nearest-even conversion
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+void layout_16(const std::vector<double>& K, int H, int HQ, bool bf16, std::vector<uint16_t>& out) {
+  const int nb = (HQ + 3) / 4, nj8 = (HQ + 7) / 8;
+  out.assign((size_t)nb * nj8 * 64 * 8, 0);
+  for (int b = 0; b < nb; ++b)
+    for (int jj = 0; jj < nj8; ++jj)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 8; ++e) {
+          const int r = out_row(b, lane & 15, HQ, H);
+          const int c = in_row(lane >> 4, 8 * jj + e, HQ, H);
+          const float v = (r >= 0 && c >= 0) ? (float)K[(size_t)r * H + c] : 0.0f;
+          out[(((size_t)b * nj8 + jj) * 64 + lane) * 8 + e] =
+              bf16 ? float_to_bf16_rne(v) : float_to_f16_rne(v);
+        }
+}
+
+}  // namespace prism

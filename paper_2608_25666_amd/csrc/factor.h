@@ -1,0 +1,42 @@
+// Host-side construction of the reusable x-update factor and its on-chip layouts.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace prism {
+
+// Rows of one lane group ("chunk") for horizon H: the 4 lane groups of a wave
+// each hold HQ consecutive steps of a column, HQ = ceil(H / 4).
+inline int chunk_rows(int H) { return (H + 3) / 4; }
+
+// K (H*H, row-major) and k (H) of x = K r + k v0, the solution of the
+// equality-constrained primal system with P = I + rho C^T C, C = [I; L; D1; D2].
+// Returns false if P is not positive definite (cannot happen for rho > 0).
+bool build_factor(int H, double rho, std::vector<double>& K, std::vector<double>& k);
+
+// FP32 A-operand fragments for v_mfma_f32_16x16x4_f32, read as one float4 per
+// lane per (output block b, group of four k-steps jj):
+//   index ((b * NJ4 + jj) * 64 + lane) * 4 + e,   k-step j = 4*jj + e.
+// NB = ceil(HQ/4) output blocks, NJ4 = ceil(HQ/4).
+void layout_f32(const std::vector<double>& K, int H, int HQ, std::vector<float>& out);
+
+// 16-bit A-operand fragments for v_mfma_f32_16x16x32_{bf16,f16}: 8 values per
+// lane per (b, k-step jj), index ((b * NJ8 + jj) * 64 + lane) * 8 + e,
+// NJ8 = ceil(HQ/8). bf16 = true selects bfloat16, otherwise IEEE half. RNE.
+void layout_16(const std::vector<double>& K, int H, int HQ, bool bf16, std::vector<uint16_t>& out);
+
+// Byte sizes of the two layouts.
+inline size_t f32_frag_bytes(int HQ) {
+  const int nb = (HQ + 3) / 4;
+  return (size_t)nb * ((HQ + 3) / 4) * 64 * 4 * sizeof(float);
+}
+inline size_t b16_frag_bytes(int HQ) {
+  const int nb = (HQ + 3) / 4;
+  return (size_t)nb * ((HQ + 7) / 8) * 64 * 8 * sizeof(uint16_t);
+}
+
+uint16_t float_to_bf16_rne(float f);
+uint16_t float_to_f16_rne(float f);
+
+}  // namespace prism

@@ -1,0 +1,54 @@
+// Launch arguments shared by the host library and the device kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace prism {
+
+constexpr int kMaxJoints = 64;   // PRISM_MAX_JOINTS
+constexpr int kWaves = 4;        // waves per workgroup
+constexpr int kTileCols = 16;    // samples per tile (MFMA N dimension)
+
+enum GemmPrec : int { GEMM_F32 = 0, GEMM_BF16 = 1, GEMM_F16 = 2 };
+
+// Row bounds of one joint in velocity units, in the kernel's affine form:
+//   velocity  s = x_k                          in [v_min, v_max]
+//   position  s = sum_{i<=k} x_i               in [(q_min-q0)/dt, (q_max-q0)/dt]
+//   accel.    s = x_k - x_{k-1}, x_0 := v0     in [a_min dt, a_max dt]
+//   jerk      s = a_k - a_{k-1}, a_1 := 0      in [j_min dt^2, j_max dt^2]
+// (1-based steps; the jerk row of step 1 is identically zero and unused).
+struct JointRowParams {
+  float lb[4];
+  float ub[4];
+  float v0;
+  float pad[3];
+};
+
+struct SolveKernelArgs {
+  const float* xin;      // [N][H][nj]
+  float* xout;           // [N][H][nj]
+  float* rp;             // [N][nj] or null
+  float* rd;             // [N][nj] or null
+  int* itout;            // [N][nj] or null
+  const float* xw;       // warm x [N][H][nj] or null
+  const float* uw;       // warm u [N][nj][4][H] or null
+  float* uout;           // u out [N][nj][4][H] or null
+  const void* frag;      // FP32 fragments, then 16-bit fragments (reduced forms)
+  int* counter;          // tile counter, zero at launch
+  int N, H, nj, ntiles;
+  int iters, check_every, tail, tolmode;
+  float rho, alpha, tol;
+  int frag_f32_bytes, frag_16_bytes;
+  JointRowParams jp[kMaxJoints];
+};
+
+struct FeasKernelArgs {
+  const float* x;        // [N][H][nj]
+  double* viol;          // [N][nj][5]
+  const double* bounds;  // device [8][nj]: q_min, q_max, v_min, v_max, a_min, a_max, j_min, j_max
+  int N, H, nj;
+  double dt;
+  double q0[kMaxJoints], v0[kMaxJoints];
+};
+
+}  // namespace prism

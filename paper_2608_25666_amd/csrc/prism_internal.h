@@ -1,0 +1,40 @@
+// Library-internal declarations shared by the ABI front ends (single solve,
+// batched solve, server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <vector>
+
+#include "admm_kernels.h"
+#include "kernel_args.h"
+#include "prism_proj.h"
+
+constexpr int kCounterRing = 1024;   // tile counters per handle (in-flight early-exit solves)
+
+struct prism_proj_s {
+  int H = 0, nj = 0, HQ = 0, device = 0;
+  double dt = 0.0, rho = 0.0;
+  std::vector<double> bnd;          // [8][nj]: q_min q_max v_min v_max a_min a_max j_min j_max
+  std::vector<double> K, k;         // FP64 master factor
+  prism_options_t opts{};
+  void* frag_bf16 = nullptr;        // device: FP32 fragments then BF16 fragments
+  void* frag_f16 = nullptr;         // device: FP32 fragments then FP16 fragments
+  double* d_bounds = nullptr;       // device copy of bnd
+  int* d_counters = nullptr;        // ring of tile counters for early-exit solves
+  std::atomic<unsigned> next_counter{0};
+  int f32_bytes = 0, b16_bytes = 0;
+};
+
+namespace prism {
+
+// Row bounds of every joint for boundary values (q0, v0); PRISM_EINFEASIBLE if
+// the first rows (fixed by x_1 = v0) cannot hold.
+prism_status_t fill_joint_params(const prism_proj_s* p, const double* q0, const double* v0,
+                                 JointRowParams* jp);
+SolveKernelFn pick_kernel(int HQ, bool exact, int precision);
+int solve_lds_bytes(const prism_proj_s* p, int precision);
+hipError_t launch_feasibility(const FeasKernelArgs& a, hipStream_t stream);
+
+}  // namespace prism

@@ -1,0 +1,146 @@
+"""Thin Python front end of the C ABI: argument marshalling only.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+projection runs in the library's kernels. Tensors must live on the GPU that
+was current when the Projector was created.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+def options(precision: int = L.PREC_FP32, fp32_tail: int = 0, alpha: float = 1.0,
+            tol: float = 0.0, check_every: int = 10) -> L.Options:
+    o = L.Options()
+    L.lib().prism_options_default(C.byref(o))
+    o.precision = precision
+    o.fp32_tail = fp32_tail
+    o.alpha = alpha
+    o.tol = tol
+    o.check_every = check_every
+    return o
+
+
+def _bounds_struct(bounds, nj):
+    arrs = [L.dbl_array(np.broadcast_to(np.asarray(b, dtype=np.float64), (nj,)))
+            for b in (bounds.q_min, bounds.q_max, bounds.v_min, bounds.v_max,
+                      bounds.a_min, bounds.a_max, bounds.j_min, bounds.j_max)]
+    s = L.Bounds(*[C.cast(a, C.POINTER(C.c_double)) for a in arrs])
+    return s, arrs
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Projector:
+    """Handle for one (H, joints, dt, bounds, rho) problem family (prism_proj_create)."""
+
+    def __init__(self, H: int, n_joints: int, dt: float, bounds, rho: float = 1.0):
+        self.H, self.nj, self.dt, self.rho = int(H), int(n_joints), float(dt), float(rho)
+        self.bounds = bounds
+        b, keep = _bounds_struct(bounds, self.nj)
+        h = C.c_void_p()
+        L.check(L.lib().prism_proj_create(self.H, self.nj, self.dt, C.byref(b), self.rho,
+                                          C.byref(h)), "prism_proj_create")
+        self._h = h
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().prism_proj_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, opts: L.Options):
+        L.check(L.lib().prism_proj_set_options(self._h, C.byref(opts)), "prism_proj_set_options")
+
+    def factor(self):
+        K = np.zeros((self.H, self.H))
+        k = np.zeros(self.H)
+        L.check(L.lib().prism_proj_get_factor(
+            self._h, K.ctypes.data_as(C.POINTER(C.c_double)),
+            k.ctypes.data_as(C.POINTER(C.c_double))), "prism_proj_get_factor")
+        return K, k
+
+    def solve(self, samples, q0, v0, iters: int, opts: Optional[L.Options] = None,
+              out=None, r_primal=None, r_dual=None, iters_out=None, x_warm=None,
+              u_warm=None, u_out=None, stream=None):
+        """Project samples ([N][H][nj] float32 on the GPU). Asynchronous on the stream.
+
+        Returns (v_out, r_primal, r_dual); pass preallocated tensors to avoid
+        allocation. iters_out / u_out are filled when given.
+        """
+        import torch
+        N = int(samples.shape[0])
+        assert samples.dtype == torch.float32 and samples.is_cuda and samples.is_contiguous()
+        assert tuple(samples.shape[1:]) == (self.H, self.nj)
+        dev = samples.device
+        if out is None:
+            out = torch.empty_like(samples)
+        if r_primal is None:
+            r_primal = torch.empty((N, self.nj), dtype=torch.float32, device=dev)
+        if r_dual is None:
+            r_dual = torch.empty((N, self.nj), dtype=torch.float32, device=dev)
+        q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
+        v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
+        a = L.SolveArgs()
+        a.v_samples = samples.data_ptr()
+        a.N = N
+        a.iters = int(iters)
+        a.q0 = C.cast(q0a, C.POINTER(C.c_double))
+        a.v0 = C.cast(v0a, C.POINTER(C.c_double))
+        a.v_out = out.data_ptr()
+        a.r_primal = r_primal.data_ptr()
+        a.r_dual = r_dual.data_ptr()
+        a.iters_out = None if iters_out is None else iters_out.data_ptr()
+        a.x_warm = None if x_warm is None else x_warm.data_ptr()
+        a.u_warm = None if u_warm is None else u_warm.data_ptr()
+        a.u_out = None if u_out is None else u_out.data_ptr()
+        a.opts = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
+        L.check(L.lib().prism_proj_solve_ex(self._h, C.byref(a), _stream(stream)),
+                "prism_proj_solve_ex")
+        return out, r_primal, r_dual
+
+    def feasibility(self, v, q0, v0, out=None, stream=None):
+        """FP64 per-column violations [N][nj][5]: position, velocity, acceleration, jerk, |x1-v0|."""
+        import torch
+        N = int(v.shape[0])
+        if out is None:
+            out = torch.empty((N, self.nj, 5), dtype=torch.float64, device=v.device)
+        q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
+        v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
+        L.check(L.lib().prism_proj_feasibility(self._h, _ptr(v), N, q0a, v0a, _ptr(out),
+                                               _stream(stream)), "prism_proj_feasibility")
+        return out
+
+
+def factor_host(H: int, rho: float):
+    """prism_factor_host: the FP64 reduced inverse (K, k) built on the host."""
+    K = np.zeros((H, H))
+    k = np.zeros(H)
+    L.check(L.lib().prism_factor_host(H, rho, K.ctypes.data_as(C.POINTER(C.c_double)),
+                                      k.ctypes.data_as(C.POINTER(C.c_double))),
+            "prism_factor_host")
+    return K, k

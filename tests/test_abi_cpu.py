@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/prism_proj.h, rejects bad arguments before touching the
+device, and its host-side FP64 factor equals the oracle's (independent code)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import factor as ofactor, problem
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prism_proj.h")
+
+
+def _lib():
+    from paper_2608_25666_amd import _lib as L
+    return L, L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(prism_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.prism_abi_version() == 1
+
+
+def test_status_strings_and_defaults():
+    L, lib = _lib()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.prism_status_str(s)
+    o = L.Options()
+    lib.prism_options_default(C.byref(o))
+    assert o.precision == 0 and o.alpha == 1.0 and o.tol == 0.0 and o.check_every == 10
+
+
+@pytest.mark.parametrize("H,rho", [(2, 1.0), (5, 1.0), (20, 1.0), (50, 1.0), (100, 1.0), (128, 0.5),
+                                   (33, 3.0)])
+def test_host_factor_matches_oracle(H, rho):
+    from paper_2608_25666_amd import factor_host
+    K, k = factor_host(H, rho)
+    lim = problem.joint_limits(W.UR5E_BIMANUAL_BOUNDS(1), 0)
+    C_ = problem.velocity_unit_rows(H, 0.02, lim, 0.0, 0.0).C
+    Ko, ko = ofactor.reduced_inverse(ofactor.penalty_matrix(C_, rho))
+    np.testing.assert_allclose(K, Ko, atol=1e-10 * max(1.0, np.abs(Ko).max()))
+    np.testing.assert_allclose(k, ko, atol=1e-10)
+    assert np.all(K[0] == 0.0) and np.all(K[:, 0] == 0.0)
+
+
+def test_factor_is_independent_of_dt():
+    """After the velocity-unit scaling C = [I; L; D1; D2] is unit-free: K depends on H, rho only."""
+    lim = problem.joint_limits(W.UR5E_BIMANUAL_BOUNDS(1), 0)
+    a = problem.velocity_unit_rows(30, 0.02, lim, 0.0, 0.0).C
+    b = problem.velocity_unit_rows(30, 0.05, lim, 0.0, 0.0).C
+    np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+def _bounds(nj, lo=-1.0, hi=1.0):
+    arrs = [(C.c_double * nj)(*([lo if i % 2 == 0 else hi] * nj)) for i in range(8)]
+    L, _ = _lib()
+    return L.Bounds(*[C.cast(a, C.POINTER(C.c_double)) for a in arrs]), arrs
+
+
+@pytest.mark.parametrize("H,nj,dt,rho", [(1, 2, 0.1, 1.0), (129, 2, 0.1, 1.0), (10, 0, 0.1, 1.0),
+                                         (10, 65, 0.1, 1.0), (10, 2, 0.0, 1.0),
+                                         (10, 2, float("nan"), 1.0), (10, 2, 0.1, 0.0),
+                                         (10, 2, 0.1, -1.0), (10, 2, 0.1, float("inf"))])
+def test_create_rejects_bad_arguments(H, nj, dt, rho):
+    L, lib = _lib()
+    b, keep = _bounds(max(nj, 1))
+    h = C.c_void_p()
+    assert lib.prism_proj_create(H, nj, dt, C.byref(b), rho, C.byref(h)) == L.PRISM_EINVAL
+    assert not h.value
+
+
+def test_create_rejects_inverted_or_nonfinite_bounds():
+    L, lib = _lib()
+    h = C.c_void_p()
+    b, keep = _bounds(3, lo=1.0, hi=-1.0)
+    assert lib.prism_proj_create(10, 3, 0.1, C.byref(b), 1.0, C.byref(h)) == L.PRISM_EINVAL
+    b, keep = _bounds(3, lo=-float("inf"), hi=1.0)
+    assert lib.prism_proj_create(10, 3, 0.1, C.byref(b), 1.0, C.byref(h)) == L.PRISM_EINVAL
+    assert lib.prism_proj_create(10, 3, 0.1, None, 1.0, C.byref(h)) == L.PRISM_EINVAL
+
+
+def test_null_handle_calls_are_rejected():
+    L, lib = _lib()
+    o = L.Options()
+    lib.prism_options_default(C.byref(o))
+    assert lib.prism_proj_set_options(None, C.byref(o)) == L.PRISM_EINVAL
+    assert lib.prism_proj_solve(None, None, 0, None, None, 0, None, None, None, None) == L.PRISM_EINVAL
+    a = L.SolveArgs()
+    assert lib.prism_proj_solve_ex(None, C.byref(a), None) == L.PRISM_EINVAL
+    assert lib.prism_proj_horizon(None) == -1
+    lib.prism_proj_destroy(None)
+    assert lib.prism_factor_host(1, 1.0, None, None) == L.PRISM_EINVAL

@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance (FP32 form): max-abs 1e-4 rad/s on x at equal iteration counts.
+Residuals: |r_gpu - r_oracle| <= 1e-4 + 1e-3 r (FP32 rounding of the row
+sums; the dual residual is formed as rho C^T e - d on the GPU and as
+x - x~ + C^T y in the oracle, equal in exact arithmetic).
+Columns are independent (Sec. III-D "Joint-wise separability"), so at full
+sizes the oracle checks a sample of columns computed one joint at a time.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import admm, feasibility
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-4
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def gpu_solve(req, iters, opts=None, samples=None, **kw):
+    torch = _torch()
+    from paper_2608_25666_amd import Projector
+    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho)
+    s = req.samples if samples is None else samples
+    x = torch.from_numpy(np.ascontiguousarray(s)).cuda()
+    it = torch.zeros((x.shape[0], req.nj), dtype=torch.int32, device="cuda")
+    out, rp, rd = P.solve(x, req.q0, req.v0, iters, opts=opts, iters_out=it, **kw)
+    torch.cuda.synchronize()
+    res = (out.cpu().numpy(), rp.cpu().numpy(), rd.cpu().numpy(), it.cpu().numpy())
+    P.close()
+    return res
+
+
+def check_residuals(rp, rd, O, sel=slice(None)):
+    np.testing.assert_allclose(rp, O.r_p[sel], atol=1e-4, rtol=1e-3)
+    np.testing.assert_allclose(rd, O.r_d[sel], atol=1e-4, rtol=1e-3)
+
+
+def test_config1_fp32_matches_oracle():
+    r = W.config1()
+    x, rp, rd, it = gpu_solve(r, r.iters)
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
+    err = np.abs(x - O.x).max()
+    print(f"config1 fp32 max-abs vs oracle: {err:.3e}")
+    assert err <= TOL_X
+    check_residuals(rp, rd, O)
+    assert np.all(it == r.iters)
+
+
+def test_config2_full_size_sampled_columns():
+    """N=2048, H=50 (not a multiple of 4), 12 joints, 100 iterations; oracle on 40 samples."""
+    r = W.config2()
+    x, rp, rd, it = gpu_solve(r, r.iters)
+    pick = np.unique(np.r_[np.arange(0, 24), np.arange(1000, 1008), np.arange(2032, 2048)])
+    O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
+    err = np.abs(x[pick] - O.x).max()
+    print(f"config2 fp32 max-abs vs oracle (sampled): {err:.3e}")
+    assert err <= TOL_X
+    check_residuals(rp[pick], rd[pick], O)
+
+
+@pytest.mark.parametrize("H,N,nj,dt,kind", [
+    (2, 5, 1, 0.05, "white"),      # smallest horizon: six padding rows
+    (3, 17, 2, 0.05, "white"),     # ragged tile
+    (7, 33, 3, 0.1, "white"),      # H < 4*HQ with HQ = 2
+    (20, 37, 2, 0.05, "white"),    # exact fit (4 x 5), ragged N
+    (50, 19, 3, 0.02, "smooth"),   # two padding rows
+    (63, 16, 1, 0.02, "smooth"),   # one padding row
+    (100, 21, 2, 0.02, "smooth"),  # exact fit (4 x 25)
+    (101, 9, 1, 0.02, "smooth"),   # three padding rows
+    (128, 16, 2, 0.02, "smooth"),  # largest horizon
+])
+def test_shapes_and_ragged_tails(H, N, nj, dt, kind):
+    r = W.make_request(H * 100 + N, N=N, H=H, nj=nj, dt=dt, kind=kind, sigma=1.5)
+    iters = 60
+    x, rp, rd, it = gpu_solve(r, iters)
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=iters)
+    err = np.abs(x - O.x).max()
+    print(f"H={H} N={N} nj={nj}: max-abs {err:.3e}")
+    assert err <= TOL_X
+    check_residuals(rp, rd, O)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.6])
+def test_over_relaxation(alpha):
+    r = W.make_request(5, N=40, H=30, nj=2, dt=0.05, kind="white", sigma=1.0)
+    from paper_2608_25666_amd import options
+    x, rp, rd, it = gpu_solve(r, 80, opts=options(alpha=alpha))
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=80, alpha=alpha)
+    assert np.abs(x - O.x).max() <= TOL_X
+    check_residuals(rp, rd, O)
+
+
+def test_zero_iterations_and_empty_batch():
+    torch = _torch()
+    r = W.make_request(8, N=20, H=12, nj=2, dt=0.05, kind="white")
+    x, rp, rd, it = gpu_solve(r, 0)
+    want = r.samples.astype(np.float64).copy()
+    want[:, 0, :] = r.v0[None, :]
+    np.testing.assert_allclose(x, want, atol=1e-6)
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=0)
+    check_residuals(rp, rd, O)
+    from paper_2608_25666_amd import Projector
+    P = Projector(r.H, r.nj, r.dt, r.bounds)
+    e = torch.zeros((0, r.H, r.nj), dtype=torch.float32, device="cuda")
+    P.solve(e, r.q0, r.v0, 10)
+    torch.cuda.synchronize()
+
+
+def test_feasible_input_returned_bit_identical():
+    """x~ feasible with x~_1 = v0: the incremental update leaves it untouched bit for bit."""
+    H, nj, dt = 24, 3, 0.05
+    t = np.arange(1, H + 1) * dt
+    base = np.stack([0.2 * np.sin(2 * np.pi * 0.4 * t + p) for p in (0.0, 0.7, 1.9)], axis=1)
+    samples = np.repeat(base[None], 32, axis=0).astype(np.float32)
+    samples += np.linspace(-0.05, 0.05, 32, dtype=np.float32)[:, None, None]
+    v0 = samples[0, 0, :].astype(np.float64)
+    samples[:, 0, :] = samples[0, 0, :]
+    r = W.Request(H=H, nj=nj, dt=dt, bounds=W.UR5E_BIMANUAL_BOUNDS(nj), q0=np.zeros(nj), v0=v0,
+                  samples=samples)
+    viol = feasibility.max_violation(samples.astype(np.float64), dt, r.bounds, r.q0, r.v0)
+    assert max(viol.values()) == 0.0
+    x, rp, rd, it = gpu_solve(r, 50)
+    np.testing.assert_array_equal(x, samples)
+    assert np.all(rp == 0.0) and np.all(rd == 0.0)
+
+
+def test_output_may_alias_input():
+    torch = _torch()
+    from paper_2608_25666_amd import Projector
+    r = W.make_request(9, N=48, H=20, nj=3, dt=0.05, kind="white")
+    P = Projector(r.H, r.nj, r.dt, r.bounds)
+    x = torch.from_numpy(r.samples).cuda()
+    ref, _, _ = P.solve(x.clone(), r.q0, r.v0, 40)
+    P.solve(x, r.q0, r.v0, 40, out=x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, ref)
+
+
+def test_nan_input_gives_nan_output_and_residual():
+    r = W.make_request(10, N=32, H=16, nj=2, dt=0.05, kind="white")
+    s = r.samples.copy()
+    s[3, 5, 1] = np.nan
+    x, rp, rd, it = gpu_solve(r, 20, samples=s)
+    assert np.isnan(x[3, :, 1]).any() and np.isnan(rp[3, 1]) and np.isnan(rd[3, 1])
+    assert np.isfinite(x[4]).all() and np.isfinite(x[3, :, 0]).all()
+
+
+def test_feasibility_kernel_matches_oracle():
+    torch = _torch()
+    from paper_2608_25666_amd import Projector
+    r = W.make_request(11, N=40, H=30, nj=3, dt=0.05, kind="white", sigma=2.0)
+    P = Projector(r.H, r.nj, r.dt, r.bounds)
+    v = torch.from_numpy(r.samples).cuda()
+    out = P.feasibility(v, r.q0, r.v0)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = feasibility.violations(r.samples.astype(np.float64), r.dt, r.bounds, r.q0, r.v0)
+    for k, key in enumerate(("pos", "vel", "acc", "jerk", "eq")):
+        np.testing.assert_allclose(got[:, :, k], want[key], rtol=1e-12, atol=1e-9)
+
+
+def test_infeasible_boundary_rejected():
+    torch = _torch()
+    from paper_2608_25666_amd import Projector, PrismError
+    r = W.make_request(12, N=16, H=10, nj=2, dt=0.05, kind="white")
+    P = Projector(r.H, r.nj, r.dt, r.bounds)
+    x = torch.from_numpy(r.samples).cuda()
+    bad = r.v0.copy()
+    bad[1] = 5.0                      # outside |v| <= 3.14
+    with pytest.raises(PrismError) as e:
+        P.solve(x, r.q0, bad, 10)
+    assert e.value.status == -4
