@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark: projected trajectories per second at residual <= 1e-3 on one MI355X.
+
+Workload (default): 2 arms x 6 joints = 12 joints, N = 2048 sampled velocity
+trajectories, horizon H = 50, dt = 0.02 s, |q| <= 2 pi, |v| <= 3.14, |a| <= 8,
+|j| <= 60; samples = smooth three-sinusoid base + N(0, 0.5^2) noise; rho = 1.
+A step projects the whole batch until every 16-sample group of each joint has
+max(r_primal, r_dual) <= 1e-3 (checked every 10 iterations, capped at 20000).
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line. Extra fields: per-step p50/p99 latency, iteration
+statistics, the fixed-100-iteration throughput, a roofline object for the
+solve kernel (timed live with HIP events on the solve's stream) and the FP64
+oracle timed on the host cores on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16|fp16]
+                    [--alpha A] [--no-cpu-baseline] [--iters-cap C]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_F32_TFLOPS = 157.3
+PEAK_MFMA_B16_TFLOPS = 2500.0
+# FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations per second
+# (one add/sub/max/med3/fma per lane per cycle; packed FP32 is not used).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def valu_ops_per_col_iter(H: int) -> float:
+    """Algorithmic FP32 VALU operations of one column-iteration.
+
+    Forward rows C x: position prefix sums (H), acceleration (H) and jerk (H)
+    differences. Row update on 4H-1 rows: t, z = clip(t), q, w (5 each).
+    Transpose C^T w: position suffix sums (H), jerk/acceleration combination
+    (2H) and difference (H), block sums (2H). Defect d: 3H.
+    """
+    return 3 * H + 5 * (4 * H - 1) + 6 * H + 3 * H
+
+
+def mfma_flops_per_col_iter(H: int) -> float:
+    """x += K d with the nonzero (H-1) x (H-1) block of K."""
+    return 2.0 * (H - 1) ** 2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--iters-cap", type=int, default=20000)
+    ap.add_argument("--fp32-tail", type=int, default=0)
+    ap.add_argument("--N", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="time a fixed iteration count instead of the residual target")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the fixed-100-iteration section (for single-mode profiles)")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="samples (all joints) for the oracle")
+    return ap.parse_args()
+
+
+def cpu_baseline(req, tol, check_every, cap, alpha, nsamp):
+    """The FP64 oracle on the first nsamp samples (all joints), timed on the host."""
+    from oracle import admm
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    S = req.samples[:nsamp]
+    t0 = time.perf_counter()
+    O = admm.solve_request(S, req.H, req.dt, req.bounds, req.q0, req.v0, rho=req.rho,
+                           alpha=alpha, iters=cap, tol=tol, check_every=check_every)
+    dt = time.perf_counter() - t0
+    return {"value": nsamp / dt, "unit": "trajectories/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"first {nsamp} samples x {req.nj} joints of the benchmark batch, FP64 "
+                      f"NumPy oracle to residual <= {tol:g} (check every {check_every}); "
+                      f"{dt:.1f} s; max group iterations {int(O.iters.max())}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: every column is an "
+                          "independent QP, see DESIGN.md for how the batch would shard; "
+                          "run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
+
+    prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    req = W.config2(N=a.N)
+    dev = torch.device("cuda:0")
+    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho)
+    x = torch.from_numpy(req.samples).to(dev)
+    out = torch.empty_like(x)
+    rp = torch.empty((req.N, req.nj), dtype=torch.float32, device=dev)
+    rd = torch.empty_like(rp)
+    it = torch.empty((req.N, req.nj), dtype=torch.int32, device=dev)
+    fixed = a.fixed_iters > 0
+    opts = options(precision=prec, alpha=a.alpha, tol=0.0 if fixed else a.tol,
+                   check_every=a.check_every, fp32_tail=a.fp32_tail)
+    n_it = a.fixed_iters if fixed else a.iters_cap
+    stream = torch.cuda.current_stream()
+
+    def step():
+        P.solve(x, req.q0, req.v0, n_it, opts=opts, out=out, r_primal=rp, r_dual=rd,
+                iters_out=it, stream=stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        step()
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([s.elapsed_time(e) for s, e in ev])            # ms, solve launch on its stream
+    ms_step = wall * 1e3 / a.steps
+    iters = it.cpu().numpy()
+    res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+    converged = float(np.mean(res <= a.tol))
+
+    # fixed-count throughput (the configuration's 100 iterations)
+    fixed_ms = float("nan")
+    if not a.no_extras:
+        fopts = options(precision=prec, alpha=a.alpha, fp32_tail=a.fp32_tail)
+        for _ in range(2):
+            P.solve(x, req.q0, req.v0, 100, opts=fopts, out=out, r_primal=rp, r_dual=rd,
+                    stream=stream)
+        torch.cuda.synchronize()
+        fe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(10)]
+        for s, e in fe:
+            s.record(stream)
+            P.solve(x, req.q0, req.v0, 100, opts=fopts, out=out, r_primal=rp, r_dual=rd,
+                    stream=stream)
+            e.record(stream)
+        torch.cuda.synchronize()
+        fixed_ms = float(np.mean([s.elapsed_time(e) for s, e in fe]))
+
+    # roofline of the solve kernel over the timed region
+    H = req.H
+    col_iters = float(iters.sum())
+    valu = valu_ops_per_col_iter(H) * col_iters
+    mflop = mfma_flops_per_col_iter(H) * col_iters
+    kern_s = float(per.mean()) * 1e-3
+    t_valu = valu / (PEAK_VALU_TOPS * 1e12)
+    peak_mfma = PEAK_MFMA_F32_TFLOPS if prec == PREC_FP32 else PEAK_MFMA_B16_TFLOPS
+    t_mfma = mflop / (peak_mfma * 1e12)
+    if t_valu >= t_mfma:
+        ach = valu / kern_s / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_VALU_TOPS}
+    else:
+        ach = mflop / kern_s / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": peak_mfma, "unit": "TFLOP/s",
+                "frac": ach / peak_mfma}
+    roof["traffic"] = None
+    roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
+    roof["hbm_gbs"] = (req.N * req.nj * H * 8 + req.N * req.nj * 12) / kern_s / 1e9
+    fixed_cols = req.N * req.nj * 100
+    fixed_valu = valu_ops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
+    fixed_mfma = mfma_flops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
+
+    line = {
+        "metric": ("projected trajectories/sec at residual <=1e-3" if not fixed else
+                   f"projected trajectories/sec at {a.fixed_iters} iterations"),
+        "value": req.N / (ms_step * 1e-3),
+        "unit": "trajectories/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == PREC_FP32 else ("bf16+f32" if prec == PREC_BF16 else "f16+f32"),
+        "data": "synthetic",
+        "config": {"workload": "projection QP, 12 joints, N=2048, H=50, dt=0.02, rho=1, smooth "
+                               "3-sinusoid + N(0,0.5^2) samples, residual <= 1e-3",
+                   "N": req.N, "H": H, "joints": req.nj, "dt": req.dt, "rho": req.rho,
+                   "alpha": a.alpha, "precision": a.precision, "tol": a.tol,
+                   "check_every": a.check_every, "iters_cap": a.iters_cap},
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "iterations": {"max": int(iters.max()), "mean": float(iters.mean()),
+                       "p50": float(np.median(iters)), "converged_frac": converged},
+        "fixed_100_iters": {"ms": fixed_ms, "trajectories_per_s": req.N / (fixed_ms * 1e-3),
+                            "valu_tops": fixed_valu, "valu_frac": fixed_valu / PEAK_VALU_TOPS,
+                            "mfma_tflops": fixed_mfma, "mfma_frac": fixed_mfma / peak_mfma},
+        "roofline": roof,
+    }
+    if a.no_extras:
+        line["fixed_100_iters"] = None
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(req, a.tol, a.check_every, a.iters_cap, a.alpha,
+                                            a.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

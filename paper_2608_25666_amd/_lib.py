@@ -58,6 +58,13 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7) with
+    # its own HSA runtime. Whichever loads first is the process's runtime, so let
+    # torch's load first: the library then shares it with the tensors it reads.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
