@@ -44,6 +44,16 @@ Early exit. Columns are grouped 16 samples of one joint at a time (samples
 (iteration 0, every ``check_every`` iterations, and ``max_iters``) where every
 column in it has max(r_p, r_d) <= tol.
 
+Block penalties. The paper's penalty delta is one scalar. A positive diagonal
+penalty R = rho * diag(w_V, w_Q, w_A, w_J) (one weight per constraint block)
+keeps the same splitting, the same three steps and a single reusable
+factorization (P = I + C^T R C); it only changes the metric of the augmented
+term, so the fixed point is still the projection. With weights the steps read
+    x+ : M [x; mu] = [x~ + C^T (R z - y); v0],   P = I + C^T R C
+    z+ = clip(s^ + R^-1 y, lo, hi),   y+ = y + R (s^ - z+),
+and the start is z0 = clip(s0 + R^-1 y_w), y0 = y_w + R (s0 - z0). Unit
+weights give the scalar-penalty iteration above.
+
 ``literal_joint`` runs the iteration exactly as printed (paper scaling of G,
 delta = rho, primal-space lambda, dual step delta/2) for comparison only.
 """
@@ -79,19 +89,29 @@ def residuals(C, x, xt, z, y):
     return r_p, r_d
 
 
+def block_penalty(H: int, rho: float, weights=None) -> np.ndarray:
+    """Per-row penalty rho * w_b for the velocity, position, acceleration, jerk blocks."""
+    w = (1.0, 1.0, 1.0, 1.0) if weights is None else tuple(float(v) for v in weights)
+    return rho * np.concatenate([np.full(H, w[0]), np.full(H, w[1]), np.full(H, w[2]),
+                                 np.full(H - 1, w[3])])
+
+
 def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
                q0: float, v0: float, rho: float = 1.0, alpha: float = 1.0,
                iters: int = 100, tol: Optional[float] = None, check_every: int = 10,
                group: int = GROUP, warm_x: Optional[np.ndarray] = None,
-               warm_y: Optional[np.ndarray] = None) -> JointResult:
+               warm_y: Optional[np.ndarray] = None, weights=None) -> JointResult:
     """Headline ADMM for the columns of one joint.
 
     xt_cols: (ncols, H) samples x~. With ``tol`` None the iteration runs exactly
     ``iters`` times; otherwise ``iters`` is the cap and groups stop early.
+    ``weights``: block penalty weights (w_V, w_Q, w_A, w_J), default all 1.
     """
     rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
     C, lo, hi = rows.C, rows.lo[:, None], rows.hi[:, None]
-    fac = KKTFactor(penalty_matrix(C, rho))
+    Rv = block_penalty(H, rho, weights)
+    R = Rv[:, None]
+    fac = KKTFactor(np.eye(H) + C.T @ (R * C))
     xt = np.asarray(xt_cols, dtype=np.float64).T.copy()         # (H, ncols)
     ncols = xt.shape[1]
     x = (xt.copy() if warm_x is None else np.asarray(warm_x, dtype=np.float64).T.copy())
@@ -99,8 +119,8 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
     y = (np.zeros((C.shape[0], ncols)) if warm_y is None
          else np.asarray(warm_y, dtype=np.float64).T.copy())
     s0 = C @ x
-    z = np.clip(s0 + y / rho, lo, hi)
-    y = y + rho * (s0 - z)
+    z = np.clip(s0 + y / R, lo, hi)
+    y = y + R * (s0 - z)
 
     done = np.zeros(ncols, dtype=bool)
     n_done = np.full(ncols, iters, dtype=np.int64)
@@ -124,12 +144,12 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
             break
         act = ~done
         xa, za, ya = x[:, act], z[:, act], y[:, act]
-        r = xt[:, act] + rho * (C.T @ (za - ya / rho))
+        r = xt[:, act] + C.T @ (R * za - ya)
         x_new = fac.solve(r, v0)
         s = C @ x_new
         shat = alpha * s + (1.0 - alpha) * za
-        z_new = np.clip(shat + ya / rho, lo, hi)
-        y_new = ya + rho * (shat - z_new)
+        z_new = np.clip(shat + ya / R, lo, hi)
+        y_new = ya + R * (shat - z_new)
         x[:, act], z[:, act], y[:, act] = x_new, z_new, y_new
         del xa
         if l % check_every == 0 or l == iters:
@@ -151,7 +171,7 @@ def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
                   rho: float = 1.0, alpha: float = 1.0, iters: int = 100,
                   tol: Optional[float] = None, check_every: int = 10,
                   warm_x: Optional[np.ndarray] = None,
-                  warm_y: Optional[np.ndarray] = None) -> RequestResult:
+                  warm_y: Optional[np.ndarray] = None, weights=None) -> RequestResult:
     """Project every sample of a request (layout [N][H][nj]), joint by joint."""
     samples = np.asarray(samples)
     N, H_, nj = samples.shape
@@ -166,7 +186,8 @@ def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
         res = admm_joint(samples[:, :, j], H, dt, lim, float(q0[j]), float(v0[j]), rho=rho,
                          alpha=alpha, iters=iters, tol=tol, check_every=check_every,
                          warm_x=None if warm_x is None else warm_x[:, :, j],
-                         warm_y=None if warm_y is None else warm_y[:, j, :])
+                         warm_y=None if warm_y is None else warm_y[:, j, :],
+                         weights=weights)
         x[:, :, j] = res.x
         r_p[:, j] = res.r_p
         r_d[:, j] = res.r_d

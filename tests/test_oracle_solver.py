@@ -259,3 +259,60 @@ def test_kkt_factor_route_equals_reduced_inverse_route():
         z = zn
     res = admm.admm_joint(r.samples[:5, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=50)
     np.testing.assert_allclose(res.x, x.T, atol=1e-10)
+
+
+W_ACCEL = (1.0, 0.125, 4.0, 20.0)   # block weights (velocity, position, acceleration, jerk)
+
+
+def test_block_weights_keep_the_fixed_point():
+    """A diagonal block penalty changes the path, not the limit: the converged iterate
+    passes the KKT certificate and equals the unit-weight limit."""
+    r = W.make_request(31, N=12, H=20, nj=2, dt=0.05, kind="white", sigma=1.0)
+    for j in range(2):
+        lim = problem.joint_limits(r.bounds, j)
+        rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
+        a = admm.admm_joint(r.samples[:, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], alpha=1.6,
+                            iters=60000, tol=1e-11, check_every=50, weights=W_ACCEL)
+        b = admm.admm_joint(r.samples[:, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], alpha=1.6,
+                            iters=60000, tol=1e-11, check_every=50)
+        np.testing.assert_allclose(a.x, b.x, atol=1e-7)
+        for c in range(r.N):
+            xt = r.samples[c, :, j].astype(np.float64)
+            xp = exact.polish(xt, rows.C, rows.lo, rows.hi, r.v0[j], a.y[c])
+            viol, stat = exact.kkt_certificate(xp, xt, rows.C, rows.lo, rows.hi, r.v0[j])
+            assert viol < 1e-8 and stat < 1e-8
+
+
+def test_block_weighted_primal_step_solves_its_subproblem():
+    """With R = rho diag(w): x1 minimises 1/2||x-x~||^2 + 1/2||Cx - z0 + R^-1 y0||_R^2, x_1 = v0."""
+    rng = np.random.default_rng(41)
+    H, dt, rho, v0 = 18, 0.05, 1.3, 0.2
+    lim = _lim()
+    rows = problem.velocity_unit_rows(H, dt, lim, 0.0, v0)
+    R = admm.block_penalty(H, rho, W_ACCEL)
+    xt = rng.normal(0, 2, (3, H))
+    x0 = xt.copy()
+    x0[:, 0] = v0
+    s0 = x0 @ rows.C.T
+    z0 = np.clip(s0, rows.lo, rows.hi)
+    u0 = s0 - z0                                   # R^-1 y0
+    res = admm.admm_joint(xt, H, dt, lim, 0.0, v0, rho=rho, iters=1, weights=W_ACCEL)
+    x1 = res.x
+    grad = (x1 - xt) + ((x1 @ rows.C.T - z0 + u0) * R) @ rows.C
+    np.testing.assert_allclose(grad[:, 1:], 0.0, atol=1e-9)
+    np.testing.assert_allclose(res.x[:, 0], v0, atol=1e-14)
+
+
+def test_block_weighted_dual_residual_identity():
+    """alpha = 1: r_d = ||C^T R (z^L - z^{L-1})|| on rows 2..H with the block penalty."""
+    r = W.config1()
+    j = 2
+    lim = problem.joint_limits(r.bounds, j)
+    rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
+    R = admm.block_penalty(r.H, 1.0, W_ACCEL)
+    a = admm.admm_joint(r.samples[:8, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=29,
+                        weights=W_ACCEL)
+    b = admm.admm_joint(r.samples[:8, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=30,
+                        weights=W_ACCEL)
+    direct = np.max(np.abs(((b.z - a.z) * R) @ rows.C)[:, 1:], axis=1)
+    np.testing.assert_allclose(b.r_d, direct, rtol=1e-6, atol=1e-9)
