@@ -63,7 +63,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--alpha", type=float, default=1.6)
+    ap.add_argument("--weights", default="default", choices=["default", "unit"],
+                    help="block penalty weights: prism_default_block_weights(H) or all ones")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--iters-cap", type=int, default=20000)
@@ -78,7 +80,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(req, tol, check_every, cap, alpha, nsamp):
+def cpu_baseline(req, tol, check_every, cap, alpha, nsamp, weights):
     """The FP64 oracle on the first nsamp samples (all joints), timed on the host."""
     from oracle import admm
     try:
@@ -89,7 +91,8 @@ def cpu_baseline(req, tol, check_every, cap, alpha, nsamp):
     S = req.samples[:nsamp]
     t0 = time.perf_counter()
     O = admm.solve_request(S, req.H, req.dt, req.bounds, req.q0, req.v0, rho=req.rho,
-                           alpha=alpha, iters=cap, tol=tol, check_every=check_every)
+                           alpha=alpha, iters=cap, tol=tol, check_every=check_every,
+                           weights=weights)
     dt = time.perf_counter() - t0
     return {"value": nsamp / dt, "unit": "trajectories/s", "cores": int(threads),
             "kind": "oracle",
@@ -112,7 +115,8 @@ def main():
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     req = W.config2(N=a.N)
     dev = torch.device("cuda:0")
-    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho)
+    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho,
+                  weights=None if a.weights == "unit" else "default")
     x = torch.from_numpy(req.samples).to(dev)
     out = torch.empty_like(x)
     rp = torch.empty((req.N, req.nj), dtype=torch.float32, device=dev)
@@ -206,7 +210,8 @@ def main():
         "config": {"workload": "projection QP, 12 joints, N=2048, H=50, dt=0.02, rho=1, smooth "
                                "3-sinusoid + N(0,0.5^2) samples, residual <= 1e-3",
                    "N": req.N, "H": H, "joints": req.nj, "dt": req.dt, "rho": req.rho,
-                   "alpha": a.alpha, "precision": a.precision, "tol": a.tol,
+                   "alpha": a.alpha, "block_weights": P.weights or (1.0, 1.0, 1.0, 1.0),
+                   "precision": a.precision, "tol": a.tol,
                    "check_every": a.check_every, "iters_cap": a.iters_cap},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "iterations": {"max": int(iters.max()), "mean": float(iters.mean()),
@@ -220,7 +225,7 @@ def main():
         line["fixed_100_iters"] = None
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(req, a.tol, a.check_every, a.iters_cap, a.alpha,
-                                            a.cpu_sample)
+                                            a.cpu_sample, P.weights)
     print(json.dumps(line), flush=True)
 
 

@@ -11,7 +11,7 @@
  *
  * solved independently per (sample, joint) column (Sec. III-D "Joint-wise
  * separability", "Batch parallelism") with an ADMM splitting whose primal
- * system is factored once per (H, dt, rho) (Sec. III-D "Pre-computable
+ * system is factored once per (H, rho) (Sec. III-D "Pre-computable
  * factorization") and whose boundary values only change the bounds (Sec. III-D
  * "Boundary value update").
  *
@@ -114,6 +114,22 @@ void prism_options_default(prism_options_t* opts);
 prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bounds_t* bounds,
                                  double rho, prism_proj_t* out);
 
+/* prism_proj_create_ex -- as prism_proj_create with a diagonal block penalty.
+ *
+ * The penalty of the augmented term becomes R = rho * diag(w) with one weight
+ * per constraint block (block_weights[0..3]: velocity, position, acceleration,
+ * jerk rows), so P = I + C^T R C. The paper uses one scalar penalty (Sec. III-D
+ * eq. (aug_lag)); a positive diagonal penalty keeps the same three steps and one
+ * reusable factor and has the same fixed point (the projection), but can reach
+ * a residual target in far fewer iterations. block_weights = NULL gives unit
+ * weights (identical to prism_proj_create). Every weight must be > 0 and
+ * finite, else PRISM_EINVAL. u = y / (rho w_b) is the scaled dual of each row. */
+prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_bounds_t* bounds,
+                                    double rho, const double* block_weights, prism_proj_t* out);
+
+/* Recommended block weights for horizon H: (1, 2.5/H, 4, 20). Writes w[0..3]. */
+void prism_default_block_weights(int H, double* w);
+
 /* Set the handle's default options (used by prism_proj_solve). Not safe to
  * call while another thread issues solves on the same handle. */
 prism_status_t prism_proj_set_options(prism_proj_t p, const prism_options_t* opts);
@@ -190,10 +206,12 @@ int prism_proj_joints(prism_proj_t p);
 /* Copy the FP64 reduced inverse K (H*H, row-major) and k (H) built by create
  * into host arrays. Host-only; usable without a GPU via prism_factor_host. */
 prism_status_t prism_proj_get_factor(prism_proj_t p, double* K, double* k);
+prism_status_t prism_proj_get_weights(prism_proj_t p, double* w);
 
 /* Host-only factor build (no device work), same arithmetic as create:
- * K (H*H row-major) and k (H). Returns PRISM_EINVAL on bad arguments. */
-prism_status_t prism_factor_host(int H, double rho, double* K, double* k);
+ * K (H*H row-major) and k (H); w = block weights or NULL for ones.
+ * Returns PRISM_EINVAL on bad arguments. */
+prism_status_t prism_factor_host(int H, double rho, const double* w, double* K, double* k);
 
 const char* prism_status_str(prism_status_t s);
 int prism_abi_version(void);

@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
         "prism_options_default": (None, [C.POINTER(Options)]),
         "prism_proj_create": (st, [C.c_int, C.c_int, C.c_double, C.POINTER(Bounds), C.c_double,
                                    C.POINTER(H)]),
+        "prism_proj_create_ex": (st, [C.c_int, C.c_int, C.c_double, C.POINTER(Bounds),
+                                      C.c_double, C.POINTER(C.c_double), C.POINTER(H)]),
+        "prism_default_block_weights": (None, [C.c_int, C.POINTER(C.c_double)]),
+        "prism_proj_get_weights": (st, [H, C.POINTER(C.c_double)]),
         "prism_proj_set_options": (st, [H, C.POINTER(Options)]),
         "prism_proj_get_options": (st, [H, C.POINTER(Options)]),
         "prism_proj_solve": (st, [H, C.c_void_p, C.c_int, C.POINTER(C.c_double),
@@ -89,7 +93,7 @@ def load(path: str = LIB_PATH):
         "prism_proj_joints": (C.c_int, [H]),
         "prism_proj_get_factor": (st, [H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "prism_factor_host": (st, [C.c_int, C.c_double, C.POINTER(C.c_double),
-                                   C.POINTER(C.c_double)]),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "prism_status_str": (C.c_char_p, [C.c_int]),
         "prism_abi_version": (C.c_int, []),
     }

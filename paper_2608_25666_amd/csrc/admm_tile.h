@@ -19,7 +19,9 @@
 //   V: x_k   Q: sum_{i<=k} x_i   A: x_k - x_{k-1}   J: A_k - A_{k-1}.
 // One iteration (rows updated with the current s = C x):
 //   t = alpha s + q,  z = clip(t, lb, ub),  q' = t - alpha z,
-//   w = 2 z - t - s  (= z - s - u'),  d = (x~ - x) + rho C^T w,  x += K d.
+//   w = 2 z - t - s  (= z - s - u'),  d = (x~ - x) + C^T R w,  x += K d,
+// with R = rho diag(w_V, w_Q, w_A, w_J) the block penalty (one weight per
+// block; the weights enter the transposed sums as FMA coefficients).
 // This is the scaled ADMM of the paper's splitting (slack clip = Step 1,
 // primal solve = Step 2, multiplier update = Step 3, multiplier carried in the
 // constraint space), written with one state per row and an incremental
@@ -90,6 +92,7 @@ struct TileSolver {
   int a_prev, a_next, a_prev2, a_next2;   // ds_bpermute byte addresses
   float lbV, ubV, lbQ, ubQ, lbA, ubA, lbJ, ubJ, v0;
   float rho, alpha, oma;
+  float cV, cQ, cJ;   // block penalties relative to the acceleration block
 
   __device__ __forceinline__ float X(int i) const { return xb[i >> 2][i & 3]; }
 
@@ -175,9 +178,9 @@ struct TileSolver {
       float suf = 0.0f, sufe = 0.0f;
 #pragma unroll
       for (int i = HQ - 1; i >= 0; --i) {
-        suf += sw[i];
+        suf = fmaf(cQ, sw[i], suf);
         sw[i] = suf;
-        if constexpr (CHECK) { sufe += se[i]; se[i] = sufe; }
+        if constexpr (CHECK) { sufe = fmaf(cQ, se[i], sufe); se[i] = sufe; }
       }
       offw = excl_suffix(suf);
       if constexpr (CHECK) offe = excl_suffix(sufe);
@@ -187,12 +190,13 @@ struct TileSolver {
 #pragma unroll
     for (int i = 0; i < HQ; ++i) {
       float w = rowop<CHECK>(X(i), qv[i], lbV, ubV, e, u);
-      sw[i] += mask(i, w);
-      if constexpr (CHECK) { e = mask(i, e); se[i] += e; track(i, e, u, 0); }
+      sw[i] = fmaf(cV, mask(i, w), sw[i]);
+      if constexpr (CHECK) { e = mask(i, e); se[i] = fmaf(cV, e, se[i]); track(i, e, u, 0); }
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- acceleration and jerk blocks, streamed along the chunk.
-    // C_A^T w_A + C_J^T w_J = D^T v with v_k = wA_k + wJ_k - wJ_{k+1}, (D^T v)_k = v_k - v_{k+1}.
+    // C_A^T w_A + cJ C_J^T w_J = D^T v with v_k = wA_k + cJ (wJ_k - wJ_{k+1}),
+    // (D^T v)_k = v_k - v_{k+1}.
     {
       const float xl = X(HQ - 1);
       const float al = X(HQ - 1) - X(HQ - 2);
@@ -221,9 +225,9 @@ struct TileSolver {
           wj_0 = wj;
           if constexpr (CHECK) ej_0 = ej;
         } else {
-          const float v = wa_p + wj_p - wj;
+          const float v = fmaf(cJ, wj_p - wj, wa_p);
           float ve = 0.0f;
-          if constexpr (CHECK) ve = ea_p + ej_p - ej;
+          if constexpr (CHECK) ve = fmaf(cJ, ej_p - ej, ea_p);
           if (i == 1) {
             v_0 = v;
             if constexpr (CHECK) ve_0 = ve;
@@ -240,7 +244,7 @@ struct TileSolver {
       }
       float wj_n = lane_read(wj_0, a_next);
       wj_n = (g == 3) ? 0.0f : wj_n;
-      const float v_last = wa_p + wj_p - wj_n;
+      const float v_last = fmaf(cJ, wj_p - wj_n, wa_p);
       sw[HQ - 2] += v_pm - v_last;
       float v_n = lane_read(v_0, a_next);
       v_n = (g == 3) ? 0.0f : v_n;
@@ -248,7 +252,7 @@ struct TileSolver {
       if constexpr (CHECK) {
         float ej_n = lane_read(ej_0, a_next);
         ej_n = (g == 3) ? 0.0f : ej_n;
-        const float ve_last = ea_p + ej_p - ej_n;
+        const float ve_last = fmaf(cJ, ej_p - ej_n, ea_p);
         se[HQ - 2] += ve_pm - ve_last;
         float ve_n = lane_read(ve_0, a_next);
         ve_n = (g == 3) ? 0.0f : ve_n;
@@ -378,6 +382,9 @@ struct TileSolver {
     rho = A.rho;
     alpha = A.alpha;
     oma = 1.0f - A.alpha;
+    cV = A.cV;
+    cQ = A.cQ;
+    cJ = A.cJ;
 
     // ---- load the sample (and warm state). Lane bases include the chunk
     // offset so the per-row offsets i*nj are wave-uniform; rows past H read

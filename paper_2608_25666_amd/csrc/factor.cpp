@@ -2,14 +2,16 @@
 //
 // Sec. III-D, "Step 2: Primal update" (eqs. (admm_primal), (admm_KKT)) solves
 //   [P  e1][x ]   [r ]
-//   [e1' 0][mu] = [v0],   P = I + rho C^T C,
-// and "Pre-computable factorization" factors it once. Eliminating mu gives
+//   [e1' 0][mu] = [v0],   P = I + rho C^T C (scalar penalty),
+// and "Pre-computable factorization" factors it once. With a diagonal block
+// penalty R = rho diag(w) in place of the scalar penalty, P = I + C^T R C.
+// Eliminating mu gives
 //   x = K r + k v0,  K = Pi - Pi e1 e1' Pi / Pi_11,  k = Pi e1 / Pi_11,  Pi = P^-1.
 // C = [I; L; D1; D2] are the constraint rows after scaling every block to
 // velocity units (cumulative sum L, first difference D1, second difference D2
-// of Sec. III-D eqs. (pos_stack), (acc_stack), (D2_def)), so K depends on H and
-// rho only. K is symmetric, K e1 = 0 (the fixed first step never moves) and
-// K P = I - k e1'.
+// of Sec. III-D eqs. (pos_stack), (acc_stack), (D2_def)), so K depends on H,
+// rho and the block weights only. K is symmetric, K e1 = 0 (the fixed first
+// step never moves) and K P = I - k e1'.
 #include "factor.h"
 
 #include <cmath>
@@ -19,26 +21,27 @@ namespace prism {
 
 namespace {
 
-// G = C^T C for C = [I; L; D1; D2], assembled from the row definitions.
-void gram(int H, std::vector<double>& G) {
+// G = C^T diag(w) C for C = [I; L; D1; D2], assembled from the row definitions
+// (w[b] weights every row of block b).
+void gram(int H, const double w[4], std::vector<double>& G) {
   G.assign((size_t)H * H, 0.0);
-  auto add_row = [&](const std::vector<std::pair<int, double>>& row) {
+  auto add_row = [&](double wb, const std::vector<std::pair<int, double>>& row) {
     for (auto& a : row)
-      for (auto& b : row) G[(size_t)a.first * H + b.first] += a.second * b.second;
+      for (auto& b : row) G[(size_t)a.first * H + b.first] += wb * a.second * b.second;
   };
-  for (int i = 0; i < H; ++i) add_row({{i, 1.0}});                       // velocity rows
+  for (int i = 0; i < H; ++i) add_row(w[0], {{i, 1.0}});                 // velocity rows
   for (int i = 0; i < H; ++i) {                                           // position rows
     std::vector<std::pair<int, double>> row;
     for (int c = 0; c <= i; ++c) row.push_back({c, 1.0});
-    add_row(row);
+    add_row(w[1], row);
   }
   for (int i = 0; i < H; ++i) {                                           // acceleration rows
-    if (i == 0) add_row({{0, 1.0}});
-    else add_row({{i, 1.0}, {i - 1, -1.0}});
+    if (i == 0) add_row(w[2], {{0, 1.0}});
+    else add_row(w[2], {{i, 1.0}, {i - 1, -1.0}});
   }
   for (int r = 0; r + 1 < H; ++r) {                                       // jerk rows, steps 2..H
-    if (r == 0) add_row({{0, -2.0}, {1, 1.0}});
-    else add_row({{r - 1, 1.0}, {r, -2.0}, {r + 1, 1.0}});
+    if (r == 0) add_row(w[3], {{0, -2.0}, {1, 1.0}});
+    else add_row(w[3], {{r - 1, 1.0}, {r, -2.0}, {r + 1, 1.0}});
   }
 }
 
@@ -61,9 +64,10 @@ bool cholesky(int n, std::vector<double>& A) {
 
 }  // namespace
 
-bool build_factor(int H, double rho, std::vector<double>& K, std::vector<double>& k) {
+bool build_factor(int H, double rho, const double* w, std::vector<double>& K, std::vector<double>& k) {
+  const double ones[4] = {1.0, 1.0, 1.0, 1.0};
   std::vector<double> P;
-  gram(H, P);
+  gram(H, w ? w : ones, P);
   for (auto& v : P) v *= rho;
   for (int i = 0; i < H; ++i) P[(size_t)i * H + i] += 1.0;
   std::vector<double> R = P;

@@ -11,9 +11,11 @@ namespace prism {
 inline int chunk_rows(int H) { return (H + 3) / 4; }
 
 // K (H*H, row-major) and k (H) of x = K r + k v0, the solution of the
-// equality-constrained primal system with P = I + rho C^T C, C = [I; L; D1; D2].
-// Returns false if P is not positive definite (cannot happen for rho > 0).
-bool build_factor(int H, double rho, std::vector<double>& K, std::vector<double>& k);
+// equality-constrained primal system with P = I + C^T R C, C = [I; L; D1; D2]
+// and R = rho * diag(w) (w: one positive weight per constraint block, in the
+// order velocity, position, acceleration, jerk; null = all ones).
+// Returns false if P is not positive definite (cannot happen for rho, w > 0).
+bool build_factor(int H, double rho, const double* w, std::vector<double>& K, std::vector<double>& k);
 
 // FP32 A-operand fragments for v_mfma_f32_16x16x4_f32, read as one float4 per
 // lane per (output block b, group of four k-steps jj):

@@ -37,7 +37,8 @@ struct SolveKernelArgs {
   int* counter;          // tile counter, zero at launch
   int N, H, nj, ntiles;
   int iters, check_every, tail, tolmode;
-  float rho, alpha, tol;
+  float rho, alpha, tol;          // rho: penalty of the acceleration block (rho * w_A)
+  float cV, cQ, cJ;               // block weights relative to the acceleration block
   int frag_f32_bytes, frag_16_bytes;
   JointRowParams jp[kMaxJoints];
 };

@@ -16,6 +16,7 @@ constexpr int kCounterRing = 1024;   // tile counters per handle (in-flight earl
 struct prism_proj_s {
   int H = 0, nj = 0, HQ = 0, device = 0;
   double dt = 0.0, rho = 0.0;
+  double w[4] = {1.0, 1.0, 1.0, 1.0};   // block penalty weights (velocity, position, acceleration, jerk)
   std::vector<double> bnd;          // [8][nj]: q_min q_max v_min v_max a_min a_max j_min j_max
   std::vector<double> K, k;         // FP64 master factor
   prism_options_t opts{};

@@ -160,10 +160,29 @@ const char* prism_status_str(prism_status_t s) {
 
 int prism_abi_version(void) { return PRISM_PROJ_ABI_VERSION; }
 
-prism_status_t prism_factor_host(int H, double rho, double* K, double* k) {
-  if (H < 2 || H > PRISM_MAX_H || !(rho > 0.0) || !is_fin(rho) || !K || !k) return PRISM_EINVAL;
+namespace {
+bool valid_weights(const double* w) {
+  if (!w) return true;
+  for (int b = 0; b < 4; ++b)
+    if (!(w[b] > 0.0) || !is_fin(w[b])) return false;
+  return true;
+}
+}  // namespace
+
+void prism_default_block_weights(int H, double* w) {
+  if (!w) return;
+  const int h = H < 2 ? 2 : H;
+  w[0] = 1.0;
+  w[1] = 2.5 / h;
+  w[2] = 4.0;
+  w[3] = 20.0;
+}
+
+prism_status_t prism_factor_host(int H, double rho, const double* w, double* K, double* k) {
+  if (H < 2 || H > PRISM_MAX_H || !(rho > 0.0) || !is_fin(rho) || !K || !k || !valid_weights(w))
+    return PRISM_EINVAL;
   std::vector<double> Kv, kv;
-  if (!build_factor(H, rho, Kv, kv)) return PRISM_EINVAL;
+  if (!build_factor(H, rho, w, Kv, kv)) return PRISM_EINVAL;
   std::memcpy(K, Kv.data(), sizeof(double) * H * H);
   std::memcpy(k, kv.data(), sizeof(double) * H);
   return PRISM_OK;
@@ -171,7 +190,12 @@ prism_status_t prism_factor_host(int H, double rho, double* K, double* k) {
 
 prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bounds_t* bounds,
                                  double rho, prism_proj_t* out) {
-  if (!out || !bounds) return PRISM_EINVAL;
+  return prism_proj_create_ex(H, n_joints, dt, bounds, rho, nullptr, out);
+}
+
+prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_bounds_t* bounds,
+                                    double rho, const double* block_weights, prism_proj_t* out) {
+  if (!out || !bounds || !valid_weights(block_weights)) return PRISM_EINVAL;
   if (H < 2 || H > PRISM_MAX_H || n_joints < 1 || n_joints > PRISM_MAX_JOINTS) return PRISM_EINVAL;
   if (!(dt > 0.0) || !is_fin(dt) || !(rho > 0.0) || !is_fin(rho)) return PRISM_EINVAL;
   const double* arr[8] = {bounds->q_min, bounds->q_max, bounds->v_min, bounds->v_max,
@@ -190,11 +214,13 @@ prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bou
   p->HQ = std::max(2, chunk_rows(H));
   p->dt = dt;
   p->rho = rho;
+  if (block_weights)
+    for (int b = 0; b < 4; ++b) p->w[b] = block_weights[b];
   p->bnd.resize(8 * n_joints);
   for (int b = 0; b < 8; ++b)
     for (int j = 0; j < n_joints; ++j) p->bnd[b * n_joints + j] = arr[b][j];
   prism_options_default(&p->opts);
-  if (!build_factor(H, rho, p->K, p->k)) {
+  if (!build_factor(H, rho, p->w, p->K, p->k)) {
     delete p;
     return PRISM_EINVAL;
   }
@@ -247,6 +273,12 @@ void prism_proj_destroy(prism_proj_t p) {
 
 int prism_proj_horizon(prism_proj_t p) { return p ? p->H : -1; }
 int prism_proj_joints(prism_proj_t p) { return p ? p->nj : -1; }
+
+prism_status_t prism_proj_get_weights(prism_proj_t p, double* w) {
+  if (!p || !w) return PRISM_EINVAL;
+  for (int b = 0; b < 4; ++b) w[b] = p->w[b];
+  return PRISM_OK;
+}
 
 prism_status_t prism_proj_get_factor(prism_proj_t p, double* K, double* k) {
   if (!p || !K || !k) return PRISM_EINVAL;
@@ -309,7 +341,10 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.check_every = o->check_every;
   K.tolmode = (o->tol > 0.0f) ? 1 : 0;
   K.tail = (o->precision == PRISM_PREC_FP32) ? 0 : std::min(o->fp32_tail, K.tolmode ? o->fp32_tail : a->iters);
-  K.rho = (float)p->rho;
+  K.rho = (float)(p->rho * p->w[2]);
+  K.cV = (float)(p->w[0] / p->w[2]);
+  K.cQ = (float)(p->w[1] / p->w[2]);
+  K.cJ = (float)(p->w[3] / p->w[2]);
   K.alpha = o->alpha;
   K.tol = o->tol;
   K.frag_f32_bytes = p->f32_bytes;

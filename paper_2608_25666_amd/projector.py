@@ -45,16 +45,32 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-class Projector:
-    """Handle for one (H, joints, dt, bounds, rho) problem family (prism_proj_create)."""
+def default_block_weights(H: int):
+    """prism_default_block_weights: recommended (velocity, position, acceleration, jerk) weights."""
+    w = (C.c_double * 4)()
+    L.lib().prism_default_block_weights(int(H), w)
+    return tuple(w)
 
-    def __init__(self, H: int, n_joints: int, dt: float, bounds, rho: float = 1.0):
+
+class Projector:
+    """Handle for one (H, joints, dt, bounds, rho, block weights) problem family.
+
+    weights: None for the scalar penalty (prism_proj_create), "default" for
+    prism_default_block_weights(H), or four positive numbers.
+    """
+
+    def __init__(self, H: int, n_joints: int, dt: float, bounds, rho: float = 1.0,
+                 weights=None):
         self.H, self.nj, self.dt, self.rho = int(H), int(n_joints), float(dt), float(rho)
         self.bounds = bounds
+        if isinstance(weights, str) and weights == "default":
+            weights = default_block_weights(self.H)
+        self.weights = None if weights is None else tuple(float(v) for v in weights)
         b, keep = _bounds_struct(bounds, self.nj)
         h = C.c_void_p()
-        L.check(L.lib().prism_proj_create(self.H, self.nj, self.dt, C.byref(b), self.rho,
-                                          C.byref(h)), "prism_proj_create")
+        wa = None if self.weights is None else (C.c_double * 4)(*self.weights)
+        L.check(L.lib().prism_proj_create_ex(self.H, self.nj, self.dt, C.byref(b), self.rho,
+                                             wa, C.byref(h)), "prism_proj_create_ex")
         self._h = h
         del keep
 
@@ -136,11 +152,12 @@ class Projector:
         return out
 
 
-def factor_host(H: int, rho: float):
+def factor_host(H: int, rho: float, weights=None):
     """prism_factor_host: the FP64 reduced inverse (K, k) built on the host."""
     K = np.zeros((H, H))
     k = np.zeros(H)
-    L.check(L.lib().prism_factor_host(H, rho, K.ctypes.data_as(C.POINTER(C.c_double)),
+    wa = None if weights is None else (C.c_double * 4)(*[float(v) for v in weights])
+    L.check(L.lib().prism_factor_host(H, rho, wa, K.ctypes.data_as(C.POINTER(C.c_double)),
                                       k.ctypes.data_as(C.POINTER(C.c_double))),
             "prism_factor_host")
     return K, k

@@ -46,14 +46,17 @@ def test_status_strings_and_defaults():
     assert o.precision == 0 and o.alpha == 1.0 and o.tol == 0.0 and o.check_every == 10
 
 
-@pytest.mark.parametrize("H,rho", [(2, 1.0), (5, 1.0), (20, 1.0), (50, 1.0), (100, 1.0), (128, 0.5),
-                                   (33, 3.0)])
-def test_host_factor_matches_oracle(H, rho):
+@pytest.mark.parametrize("H,rho,w", [(2, 1.0, None), (5, 1.0, None), (20, 1.0, None), (50, 1.0, None),
+                                     (100, 1.0, None), (128, 0.5, None), (33, 3.0, None),
+                                     (50, 1.0, (1.0, 0.05, 4.0, 20.0)), (17, 2.0, (0.5, 1.0, 2.0, 3.0))])
+def test_host_factor_matches_oracle(H, rho, w):
+    from oracle import admm
     from paper_2608_25666_amd import factor_host
-    K, k = factor_host(H, rho)
+    K, k = factor_host(H, rho, w)
     lim = problem.joint_limits(W.UR5E_BIMANUAL_BOUNDS(1), 0)
     C_ = problem.velocity_unit_rows(H, 0.02, lim, 0.0, 0.0).C
-    Ko, ko = ofactor.reduced_inverse(ofactor.penalty_matrix(C_, rho))
+    R = admm.block_penalty(H, rho, w)
+    Ko, ko = ofactor.reduced_inverse(np.eye(H) + C_.T @ (R[:, None] * C_))
     np.testing.assert_allclose(K, Ko, atol=1e-10 * max(1.0, np.abs(Ko).max()))
     np.testing.assert_allclose(k, ko, atol=1e-10)
     assert np.all(K[0] == 0.0) and np.all(K[:, 0] == 0.0)
@@ -95,6 +98,19 @@ def test_create_rejects_inverted_or_nonfinite_bounds():
     assert lib.prism_proj_create(10, 3, 0.1, None, 1.0, C.byref(h)) == L.PRISM_EINVAL
 
 
+def test_default_block_weights_and_weight_validation():
+    L, lib = _lib()
+    w = (C.c_double * 4)()
+    lib.prism_default_block_weights(50, w)
+    assert tuple(w) == (1.0, 0.05, 4.0, 20.0)
+    b, keep = _bounds(2)
+    h = C.c_void_p()
+    bad = (C.c_double * 4)(1.0, 0.0, 1.0, 1.0)
+    assert lib.prism_proj_create_ex(10, 2, 0.1, C.byref(b), 1.0, bad, C.byref(h)) == L.PRISM_EINVAL
+    bad = (C.c_double * 4)(1.0, float("nan"), 1.0, 1.0)
+    assert lib.prism_proj_create_ex(10, 2, 0.1, C.byref(b), 1.0, bad, C.byref(h)) == L.PRISM_EINVAL
+
+
 def test_null_handle_calls_are_rejected():
     L, lib = _lib()
     o = L.Options()
@@ -105,4 +121,4 @@ def test_null_handle_calls_are_rejected():
     assert lib.prism_proj_solve_ex(None, C.byref(a), None) == L.PRISM_EINVAL
     assert lib.prism_proj_horizon(None) == -1
     lib.prism_proj_destroy(None)
-    assert lib.prism_factor_host(1, 1.0, None, None) == L.PRISM_EINVAL
+    assert lib.prism_factor_host(1, 1.0, None, None, None) == L.PRISM_EINVAL

@@ -146,3 +146,77 @@ def test_results_independent_of_batch_companions():
     x_sub, rp_sub, _, _ = _run(r, 70, None, samples=sub)
     np.testing.assert_array_equal(x_all[16:48], x_sub)
     np.testing.assert_array_equal(rp_all[16:48], rp_sub)
+
+
+W_DEF = "default"
+
+
+def _run_w(req, iters, opts, weights, samples=None, **kw):
+    import torch
+    from paper_2608_25666_amd import Projector
+    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho, weights=weights)
+    s = req.samples if samples is None else samples
+    x = torch.from_numpy(np.ascontiguousarray(s)).cuda()
+    it = torch.zeros((x.shape[0], req.nj), dtype=torch.int32, device="cuda")
+    out, rp, rd = P.solve(x, req.q0, req.v0, iters, opts=opts, iters_out=it, **kw)
+    torch.cuda.synchronize()
+    w = P.weights
+    r = out.cpu().numpy(), rp.cpu().numpy(), rd.cpu().numpy(), it.cpu().numpy(), w
+    P.close()
+    return r
+
+
+def test_block_weights_config2_sampled():
+    """Block penalty (1, 2.5/H, 4, 20), alpha 1.6, 100 iterations on config 2: FP32 parity."""
+    from paper_2608_25666_amd import options
+    r = W.config2()
+    x, rp, rd, it, w = _run_w(r, 100, options(alpha=1.6), W_DEF)
+    assert w == (1.0, 0.05, 4.0, 20.0)
+    pick = np.unique(np.r_[np.arange(0, 16), np.arange(2032, 2048)])
+    O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=100,
+                           alpha=1.6, weights=w)
+    err = np.abs(x[pick] - O.x).max()
+    print(f"config2 weighted alpha 1.6: max-abs {err:.3e}")
+    assert err <= 1e-4
+    np.testing.assert_allclose(rp[pick], O.r_p, atol=1e-4, rtol=1e-3)
+    np.testing.assert_allclose(rd[pick], O.r_d, atol=1e-4, rtol=1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_block_weights_residual_mode(prec):
+    """Residual-driven runs with the block penalty: groups stop where the oracle's do."""
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP32
+    p = PREC_FP32 if prec == "fp32" else PREC_BF16
+    r = W.make_request(26, N=48, H=50, nj=2, dt=0.02, kind="smooth")
+    x, rp, rd, it, w = _run_w(r, 5000, options(precision=p, alpha=1.6, tol=1e-3), W_DEF)
+    assert np.all(np.maximum(rp, rd) <= 1e-3)
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=5000, alpha=1.6,
+                           tol=1e-3, weights=w)
+    diff = np.abs(it - O.iters)
+    print(f"{prec}: gpu iters {np.unique(it)} oracle {np.unique(O.iters)}")
+    if prec == "fp32":
+        assert np.all((diff == 0) | (diff == 10))
+        same = diff == 0
+        assert same.mean() >= 0.8
+        np.testing.assert_allclose(x[same.all(axis=1)], O.x[same.all(axis=1)], atol=1e-4)
+    else:
+        # BF16 rounds the defect: the count may shift by a few check periods
+        assert np.all(diff <= 0.2 * O.iters + 20)
+
+
+def test_block_weights_dual_state_round_trip():
+    import torch
+    from paper_2608_25666_amd import Projector, options
+    r = W.make_request(27, N=20, H=15, nj=2, dt=0.05, kind="white", sigma=1.0)
+    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights=W_DEF)
+    xs = torch.from_numpy(r.samples).cuda()
+    u = torch.zeros((r.N, r.nj, 4, r.H), dtype=torch.float32, device="cuda")
+    x1, _, _ = P.solve(xs, r.q0, r.v0, 35, opts=options(alpha=1.6), u_out=u)
+    torch.cuda.synchronize()
+    O1 = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, alpha=1.6, iters=35,
+                            weights=P.weights)
+    np.testing.assert_allclose(x1.cpu().numpy(), O1.x, atol=1e-4)
+    ug = u.cpu().numpy()
+    ug = np.concatenate([ug[:, :, 0, :], ug[:, :, 1, :], ug[:, :, 2, :], ug[:, :, 3, 1:]], axis=2)
+    Rrow = admm.block_penalty(r.H, r.rho, P.weights)
+    np.testing.assert_allclose(ug * Rrow, O1.y, atol=1e-3)
