@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="samples (all joints) for the oracle")
+    ap.add_argument("--copy-calibrate-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (3 times): its "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic figures")
     return ap.parse_args()
 
 
@@ -113,6 +116,14 @@ def main():
     from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
 
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    if a.copy_calibrate_mb > 0:
+        nbytes = a.copy_calibrate_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     req = W.config2(N=a.N)
     dev = torch.device("cuda:0")
     P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho,

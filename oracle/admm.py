@@ -32,6 +32,8 @@ starting point, with the previous slack taken as C x0:
     s0 = C x0,   z0 = clip(s0 + y_w/rho),   y0 = y_w + rho (s0 - z0),
 where y_w is a warm multiplier (0 for a cold start). A feasible sample with
 x~_1 = v0 gives z0 = s0 and y0 = 0 and is a fixed point from the start.
+A warm start may also carry the previous slack z_w: the first pass then is an
+ordinary relaxed step s^ = alpha s0 + (1 - alpha) z_w (z_w = s0 when absent).
 
 Residuals (per column, velocity units, rad/s):
     r_p = max_i |(C x)_i - z_i|                         primal feasibility gap
@@ -100,7 +102,8 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
                q0: float, v0: float, rho: float = 1.0, alpha: float = 1.0,
                iters: int = 100, tol: Optional[float] = None, check_every: int = 10,
                group: int = GROUP, warm_x: Optional[np.ndarray] = None,
-               warm_y: Optional[np.ndarray] = None, weights=None) -> JointResult:
+               warm_y: Optional[np.ndarray] = None, weights=None,
+               warm_z: Optional[np.ndarray] = None) -> JointResult:
     """Headline ADMM for the columns of one joint.
 
     xt_cols: (ncols, H) samples x~. With ``tol`` None the iteration runs exactly
@@ -119,8 +122,10 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
     y = (np.zeros((C.shape[0], ncols)) if warm_y is None
          else np.asarray(warm_y, dtype=np.float64).T.copy())
     s0 = C @ x
-    z = np.clip(s0 + y / R, lo, hi)
-    y = y + R * (s0 - z)
+    zw = s0 if warm_z is None else np.asarray(warm_z, dtype=np.float64).T
+    shat0 = alpha * s0 + (1.0 - alpha) * zw
+    z = np.clip(shat0 + y / R, lo, hi)
+    y = y + R * (shat0 - z)
 
     done = np.zeros(ncols, dtype=bool)
     n_done = np.full(ncols, iters, dtype=np.int64)
@@ -165,13 +170,15 @@ class RequestResult:
     r_d: np.ndarray      # [N][nj]
     iters: np.ndarray    # [N][nj]
     y: np.ndarray        # [N][nj][4H-1]
+    z: np.ndarray        # [N][nj][4H-1]
 
 
 def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
                   rho: float = 1.0, alpha: float = 1.0, iters: int = 100,
                   tol: Optional[float] = None, check_every: int = 10,
                   warm_x: Optional[np.ndarray] = None,
-                  warm_y: Optional[np.ndarray] = None, weights=None) -> RequestResult:
+                  warm_y: Optional[np.ndarray] = None, weights=None,
+                  warm_z: Optional[np.ndarray] = None) -> RequestResult:
     """Project every sample of a request (layout [N][H][nj]), joint by joint."""
     samples = np.asarray(samples)
     N, H_, nj = samples.shape
@@ -181,30 +188,38 @@ def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
     r_d = np.zeros((N, nj))
     it = np.zeros((N, nj), dtype=np.int64)
     y = np.zeros((N, nj, 4 * H - 1))
+    z = np.zeros((N, nj, 4 * H - 1))
     for j in range(nj):
         lim = problem.joint_limits(bounds, j)
         res = admm_joint(samples[:, :, j], H, dt, lim, float(q0[j]), float(v0[j]), rho=rho,
                          alpha=alpha, iters=iters, tol=tol, check_every=check_every,
                          warm_x=None if warm_x is None else warm_x[:, :, j],
                          warm_y=None if warm_y is None else warm_y[:, j, :],
-                         weights=weights)
+                         weights=weights,
+                         warm_z=None if warm_z is None else warm_z[:, j, :])
         x[:, :, j] = res.x
         r_p[:, j] = res.r_p
         r_d[:, j] = res.r_d
         it[:, j] = res.iters
         y[:, j, :] = res.y
-    return RequestResult(x=x, r_p=r_p, r_d=r_d, iters=it, y=y)
+        z[:, j, :] = res.z
+    return RequestResult(x=x, r_p=r_p, r_d=r_d, iters=it, y=y, z=z)
+
+
+def shift_rows(a: np.ndarray, H: int) -> np.ndarray:
+    """Advance every row block of a [N][nj][4H-1] array by one step, repeating the last."""
+    out = np.empty_like(a)
+    for sl in problem.JointRows(C=None, lo=None, hi=None, H=H).blocks:
+        blk = a[:, :, sl]
+        out[:, :, sl] = np.concatenate([blk[:, :, 1:], blk[:, :, -1:]], axis=2)
+    return out
 
 
 def shift_state(x: np.ndarray, y: np.ndarray, H: int):
     """Warm start for the next MPC step: advance x and every row block of y by one
     step, repeating the last entry of each block (x: [N][H][nj], y: [N][nj][4H-1])."""
     xs = np.concatenate([x[:, 1:, :], x[:, -1:, :]], axis=1)
-    ys = np.empty_like(y)
-    for sl in problem.JointRows(C=None, lo=None, hi=None, H=H).blocks:
-        blk = y[:, :, sl]
-        ys[:, :, sl] = np.concatenate([blk[:, :, 1:], blk[:, :, -1:]], axis=2)
-    return xs, ys
+    return xs, shift_rows(y, H)
 
 
 # ---------------------------------------------------------------------------

@@ -316,3 +316,18 @@ def test_block_weighted_dual_residual_identity():
                         weights=W_ACCEL)
     direct = np.max(np.abs(((b.z - a.z) * R) @ rows.C)[:, 1:], axis=1)
     np.testing.assert_allclose(b.r_d, direct, rtol=1e-6, atol=1e-9)
+
+
+def test_warm_start_with_slack_at_solution_is_fixed_point():
+    """With the previous slack carried along, a converged state (x*, z*, y*) is a fixed
+    point of the warm restart for relaxation alpha != 1 as well: C x* = z*, so the
+    relaxed step reproduces z*, and y* lies in the normal cone of the box at z*."""
+    r = W.make_request(5, N=6, H=14, nj=1, dt=0.05, kind="white", sigma=1.5)
+    lim = problem.joint_limits(r.bounds, 0)
+    kw = dict(alpha=1.6, weights=W_ACCEL)
+    a = admm.admm_joint(r.samples[:, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0], iters=60000,
+                        tol=1e-12, check_every=100, **kw)
+    b = admm.admm_joint(r.samples[:, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0], iters=25,
+                        warm_x=a.x, warm_y=a.y, warm_z=a.z, **kw)
+    np.testing.assert_allclose(b.x, a.x, atol=1e-9)
+    np.testing.assert_allclose(b.y, a.y, atol=1e-8)
