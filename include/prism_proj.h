@@ -156,17 +156,20 @@ prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N,
 
 /* Extended solve: optional per-column iteration counts, warm start and dual
  * state, and per-call options.
- *   opts:      NULL = the handle's options.
- *   iters_out: device int32 [N][n_joints] or NULL: iterations performed.
- *   x_warm:    device float32 [N][H][n_joints] or NULL: initial iterate
- *              (its first step is replaced by v0). NULL = start from v_samples.
- *   u_warm:    device float32 [N][n_joints][4][H] or NULL: initial scaled dual
- *              u = y / rho per constraint row, blocks velocity, position,
- *              acceleration, jerk; entry 0 of the jerk block is unused (the
- *              jerk rows are steps 2..H). NULL = zero.
- *   u_out:     device float32 [N][n_joints][4][H] or NULL: final scaled dual in
- *              the same layout (for warm-starting the next MPC step).
- * With x_warm / u_warm the start is z0 = clip(C x0 + u0) (cold start: u0 = 0). */
+ *   opts:        NULL = the handle's options.
+ *   iters_out:   device int32 [N][n_joints] or NULL: iterations performed.
+ *   x_warm:      device float32 [N][H][n_joints] or NULL: initial iterate
+ *                (its first step is replaced by v0). NULL = start from v_samples.
+ *   state_warm:  device float32 [N][n_joints][4][H] or NULL: dual state to start
+ *                from, q = (1 - alpha) z + u per constraint row (z the slack,
+ *                u = y / (rho w_b) the scaled multiplier; with alpha = 1 it is
+ *                u). Blocks: velocity, position, acceleration, jerk rows; entry
+ *                0 of the jerk block is unused (jerk rows are steps 2..H).
+ *                NULL = cold start (previous slack C x0, multiplier 0).
+ *   state_out:   device float32 [N][n_joints][4][H] or NULL: final q, same
+ *                layout, for warm-starting the next MPC step after a shift.
+ * The first pass is a relaxed slack/multiplier step t = alpha C x0 + q0,
+ * z0 = clip(t), u0 = t - z0, with q0 = state_warm or (1 - alpha) C x0. */
 typedef struct {
   const float* v_samples;
   int32_t N;
@@ -178,8 +181,8 @@ typedef struct {
   float* r_dual;
   int32_t* iters_out;
   const float* x_warm;
-  const float* u_warm;
-  float* u_out;
+  const float* state_warm;
+  float* state_out;
   const prism_options_t* opts;
 } prism_solve_args_t;
 

@@ -46,8 +46,8 @@ class SolveArgs(C.Structure):
     _fields_ = [("v_samples", C.c_void_p), ("N", C.c_int32), ("iters", C.c_int32),
                 ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
                 ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
-                ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("u_warm", C.c_void_p),
-                ("u_out", C.c_void_p), ("opts", C.POINTER(Options))]
+                ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("state_warm", C.c_void_p),
+                ("state_out", C.c_void_p), ("opts", C.POINTER(Options))]
 
 
 _lib = None

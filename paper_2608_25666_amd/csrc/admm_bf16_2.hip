@@ -5,14 +5,14 @@ namespace prism {
 
 SolveKernelFn solve_kernel_bf16_2(int HQ, bool exact) {
   switch (HQ) {
-    case 18: return exact ? (SolveKernelFn)admm_solve_kernel<18, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<18, false, GEMM_BF16>;
-    case 19: return exact ? (SolveKernelFn)admm_solve_kernel<19, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<19, false, GEMM_BF16>;
-    case 20: return exact ? (SolveKernelFn)admm_solve_kernel<20, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<20, false, GEMM_BF16>;
-    case 21: return exact ? (SolveKernelFn)admm_solve_kernel<21, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<21, false, GEMM_BF16>;
-    case 22: return exact ? (SolveKernelFn)admm_solve_kernel<22, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<22, false, GEMM_BF16>;
-    case 23: return exact ? (SolveKernelFn)admm_solve_kernel<23, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<23, false, GEMM_BF16>;
-    case 24: return exact ? (SolveKernelFn)admm_solve_kernel<24, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<24, false, GEMM_BF16>;
-    case 25: return exact ? (SolveKernelFn)admm_solve_kernel<25, true, GEMM_BF16> : (SolveKernelFn)admm_solve_kernel<25, false, GEMM_BF16>;
+    case 18: return exact ? kernel_for<18, true, GEMM_BF16>() : kernel_for<18, false, GEMM_BF16>();
+    case 19: return exact ? kernel_for<19, true, GEMM_BF16>() : kernel_for<19, false, GEMM_BF16>();
+    case 20: return exact ? kernel_for<20, true, GEMM_BF16>() : kernel_for<20, false, GEMM_BF16>();
+    case 21: return exact ? kernel_for<21, true, GEMM_BF16>() : kernel_for<21, false, GEMM_BF16>();
+    case 22: return exact ? kernel_for<22, true, GEMM_BF16>() : kernel_for<22, false, GEMM_BF16>();
+    case 23: return exact ? kernel_for<23, true, GEMM_BF16>() : kernel_for<23, false, GEMM_BF16>();
+    case 24: return exact ? kernel_for<24, true, GEMM_BF16>() : kernel_for<24, false, GEMM_BF16>();
+    case 25: return exact ? kernel_for<25, true, GEMM_BF16>() : kernel_for<25, false, GEMM_BF16>();
     default: return nullptr;
   }
 }

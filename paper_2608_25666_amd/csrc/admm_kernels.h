@@ -11,8 +11,12 @@
 
 namespace prism {
 
+// Chunk sizes up to this one fit in 256 registers per lane, so two waves share
+// each SIMD and one wave's MFMA work overlaps the other's VALU work.
+constexpr int kMaxHQTwoWaves = 18;
+
 template <int HQ, bool EXACT, int GEMM>
-__global__ __launch_bounds__(256) void admm_solve_kernel(SolveKernelArgs A) {
+__device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   {
     // stage FP32 fragments, then the 16-bit fragments of the reduced forms
@@ -40,7 +44,24 @@ __global__ __launch_bounds__(256) void admm_solve_kernel(SolveKernelArgs A) {
   }
 }
 
+template <int HQ, bool EXACT, int GEMM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
+admm_solve_kernel_2w(SolveKernelArgs A) {
+  solve_body<HQ, EXACT, GEMM>(A);
+}
+
+template <int HQ, bool EXACT, int GEMM>
+__global__ __launch_bounds__(256) void admm_solve_kernel(SolveKernelArgs A) {
+  solve_body<HQ, EXACT, GEMM>(A);
+}
+
 using SolveKernelFn = void (*)(SolveKernelArgs);
+
+template <int HQ, bool EXACT, int GEMM>
+SolveKernelFn kernel_for() {
+  if constexpr (HQ <= kMaxHQTwoWaves) return admm_solve_kernel_2w<HQ, EXACT, GEMM>;
+  else return admm_solve_kernel<HQ, EXACT, GEMM>;
+}
 
 // Kernel for chunk size HQ (2..32), exact fit (4*HQ == H) and GEMM precision.
 SolveKernelFn solve_kernel_f32(int HQ, bool exact);

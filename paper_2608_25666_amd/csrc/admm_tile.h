@@ -136,29 +136,16 @@ struct TileSolver {
   }
 
   // Row update for every block and transposed accumulation sw = C^T w
-  // (se = C^T e on check iterations). uo: where to store u (check only).
+  // (se = C^T e and the primal residual on check iterations).
   template <bool CHECK>
-  __device__ __forceinline__ void row_update(float* __restrict__ uo, int H) {
+  __device__ __forceinline__ void row_update() {
     float e = 0.0f, u = 0.0f;
-    float* upb[4] = {nullptr, nullptr, nullptr, nullptr};
-    const bool store_u = CHECK && (uo != nullptr);   // wave-uniform
-    if constexpr (CHECK) {
-      rpm = 0.0f;
-      if (store_u) {
-        // one base per block so that every row store uses an immediate offset
-#pragma unroll
-        for (int b = 0; b < 4; ++b) upb[b] = opaque(uo + b * H + g * HQ);
-      }
-    }
+    if constexpr (CHECK) rpm = 0.0f;
     auto track = [&](int i, float ev, float uv, int blk) {
-      if constexpr (CHECK) {
-        rpm = fmaxf(rpm, fabsf(ev));
-        if (store_u) {
-          float* dst = upb[blk] + i;
-          if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
-          *dst = uv;
-        }
-      }
+      (void)i;
+      (void)uv;
+      (void)blk;
+      if constexpr (CHECK) rpm = fmaxf(rpm, fabsf(ev));
     };
     // ---- position block: s = prefix sum (chunk prefix + lower chunks' totals)
     {
@@ -414,6 +401,7 @@ struct TileSolver {
     if (g == 0) xb[0][0] = v0;                 // x_1 = v0 (eq. (A_b_def))
     const size_t ubase = ((size_t)s_ld * nj + j) * 4 * H;
     if (A.uw != nullptr) {
+      // warm state: q = (1 - alpha) z + u of the previous solve (shifted by the caller)
       const float* pu = opaque(A.uw + ubase + g * HQ);
 #pragma unroll
       for (int i = 0; i < HQ; ++i) {
@@ -424,19 +412,13 @@ struct TileSolver {
         qa[i] = ok ? pu[2 * H + r] : 0.0f;
         qj[i] = ok ? pu[3 * H + r] : 0.0f;
       }
+      if (g == 0) { qa[0] = 0.0f; qj[0] = 0.0f; }   // rows fixed by x_1 = v0 carry no dual
     } else {
 #pragma unroll
       for (int i = 0; i < HQ; ++i) { qv[i] = 0.0f; qq[i] = 0.0f; qa[i] = 0.0f; qj[i] = 0.0f; }
+      // cold start: the previous slack is C x0, so q = (1 - alpha) C x0
+      if (A.alpha != 1.0f) prep_q();
     }
-    if (g == 0) { qa[0] = 0.0f; qj[0] = 0.0f; }   // rows fixed by x_1 = v0 carry no dual
-    // per-lane u output base: columns past N write to the sink
-    float* uo = nullptr;
-    if (A.uout != nullptr) uo = col_ok ? A.uout + ubase : g_store_sink;
-
-    // The first pass takes the slack and multiplier steps from x0 with the
-    // previous slack set to C x0: q = (1 - alpha) C x0 + u0, so every pass,
-    // including this one, is the same row update.
-    if (A.alpha != 1.0f) prep_q();
 
     const bool tolmode = A.tolmode != 0;
     const bool reduced = GEMM != GEMM_F32;
@@ -447,8 +429,8 @@ struct TileSolver {
     int tail_left = -1;          // >= 0 while running FP32 iterations after convergence
     for (;;) {
       const bool chk = (it == iters) || (tolmode && (it % ce) == 0) || tail_left == 0;
-      if (chk) row_update<true>(uo, H);
-      else row_update<false>(uo, H);
+      if (chk) row_update<true>();
+      else row_update<false>();
       if (tail_left == 0) break;
       if (chk && tolmode && tail_left < 0) {
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
@@ -476,6 +458,29 @@ struct TileSolver {
         float* dst = po + i * st;
         if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
         *dst = v;
+      }
+    }
+    if (A.uout != nullptr) {
+      // relaxed dual state q = (1 - alpha) z + u per row, for warm-starting
+      float* qb = opaque(col_ok ? A.uout + ubase + g * HQ : g_store_sink);
+      const int bs = col_ok ? H : 0;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        float* d0 = qb + 0 * bs + i;
+        float* d1 = qb + 1 * bs + i;
+        float* d2 = qb + 2 * bs + i;
+        float* d3 = qb + 3 * bs + i;
+        if (!(EXACT || i < HQ - 3)) {
+          const bool ok = i < nvalid;
+          d0 = ok ? d0 : g_store_sink;
+          d1 = ok ? d1 : g_store_sink;
+          d2 = ok ? d2 : g_store_sink;
+          d3 = ok ? d3 : g_store_sink;
+        }
+        *d0 = qv[i];
+        *d1 = qq[i];
+        *d2 = qa[i];
+        *d3 = qj[i];
       }
     }
     float rp = rpm, rd = rdm;

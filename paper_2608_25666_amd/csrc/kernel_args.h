@@ -31,8 +31,8 @@ struct SolveKernelArgs {
   float* rd;             // [N][nj] or null
   int* itout;            // [N][nj] or null
   const float* xw;       // warm x [N][H][nj] or null
-  const float* uw;       // warm u [N][nj][4][H] or null
-  float* uout;           // u out [N][nj][4][H] or null
+  const float* uw;       // warm dual state q [N][nj][4][H] or null
+  float* uout;           // dual state q out [N][nj][4][H] or null
   const void* frag;      // FP32 fragments, then 16-bit fragments (reduced forms)
   int* counter;          // tile counter, zero at launch
   int N, H, nj, ntiles;

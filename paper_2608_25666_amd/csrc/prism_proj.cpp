@@ -330,8 +330,8 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.rd = a->r_dual;
   K.itout = a->iters_out;
   K.xw = a->x_warm;
-  K.uw = a->u_warm;
-  K.uout = a->u_out;
+  K.uw = a->state_warm;
+  K.uout = a->state_out;
   K.frag = (o->precision == PRISM_PREC_FP16) ? p->frag_f16 : p->frag_bf16;
   K.N = a->N;
   K.H = p->H;

@@ -102,11 +102,12 @@ class Projector:
 
     def solve(self, samples, q0, v0, iters: int, opts: Optional[L.Options] = None,
               out=None, r_primal=None, r_dual=None, iters_out=None, x_warm=None,
-              u_warm=None, u_out=None, stream=None):
+              state_warm=None, state_out=None, stream=None):
         """Project samples ([N][H][nj] float32 on the GPU). Asynchronous on the stream.
 
         Returns (v_out, r_primal, r_dual); pass preallocated tensors to avoid
-        allocation. iters_out / u_out are filled when given.
+        allocation. iters_out / state_out ([N][nj][4][H] dual state q) are filled
+        when given; x_warm / state_warm warm-start the iteration.
         """
         import torch
         N = int(samples.shape[0])
@@ -132,8 +133,8 @@ class Projector:
         a.r_dual = r_dual.data_ptr()
         a.iters_out = None if iters_out is None else iters_out.data_ptr()
         a.x_warm = None if x_warm is None else x_warm.data_ptr()
-        a.u_warm = None if u_warm is None else u_warm.data_ptr()
-        a.u_out = None if u_out is None else u_out.data_ptr()
+        a.state_warm = None if state_warm is None else state_warm.data_ptr()
+        a.state_out = None if state_out is None else state_out.data_ptr()
         a.opts = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
         L.check(L.lib().prism_proj_solve_ex(self._h, C.byref(a), _stream(stream)),
                 "prism_proj_solve_ex")

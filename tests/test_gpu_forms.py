@@ -112,27 +112,47 @@ def test_fp32_tail_after_convergence():
     assert np.all(np.maximum(rp, rd) <= 1e-3 * 1.5)
 
 
-def test_warm_start_and_dual_state_round_trip():
-    """u_out of one solve fed back with x as warm start reproduces the oracle's warm-started
-    iteration (both sides start from their own cold solve, never from each other)."""
+def oracle_state_in_kernel_rows(O, H, v0, alpha, R):
+    """q = (1 - alpha) z + y / R in the kernel's row layout [N][nj][4][H]. The kernel's
+    acceleration row of step 1 is x_1 - v0 and its jerk row of step 2 includes +v0
+    (affine parts moved from the bounds into the rows); its jerk row of step 1 is unused."""
+    N, nj = O.z.shape[:2]
+    z = O.z.copy()
+    A0, J0 = 2 * H, 3 * H                      # oracle rows: accel step 1, jerk step 2
+    z[:, :, A0] -= v0[None, :]
+    z[:, :, J0] += v0[None, :]
+    q = (1.0 - alpha) * z + O.y / R
+    out = np.zeros((N, nj, 4, H))
+    out[:, :, 0, :] = q[:, :, 0:H]
+    out[:, :, 1, :] = q[:, :, H:2 * H]
+    out[:, :, 2, :] = q[:, :, 2 * H:3 * H]
+    out[:, :, 3, 1:] = q[:, :, 3 * H:]
+    return out
+
+
+@pytest.mark.parametrize("weights", [None, "default"])
+def test_warm_start_and_dual_state_round_trip(weights):
+    """state_out of one solve fed back with x as a warm start reproduces the oracle's
+    warm-started iteration; each side restarts from its own previous solve."""
     import torch
     from paper_2608_25666_amd import Projector, options
     r = W.make_request(24, N=24, H=15, nj=2, dt=0.05, kind="white", sigma=1.0)
     H, nj, N = r.H, r.nj, r.N
-    P = Projector(H, nj, r.dt, r.bounds, r.rho)
+    alpha = 1.6
+    P = Projector(H, nj, r.dt, r.bounds, r.rho, weights=weights)
     xs = torch.from_numpy(r.samples).cuda()
-    u = torch.zeros((N, nj, 4, H), dtype=torch.float32, device="cuda")
-    x1, _, _ = P.solve(xs, r.q0, r.v0, 40, opts=options(alpha=1.6), u_out=u)
-    x2, rp2, rd2 = P.solve(xs, r.q0, r.v0, 30, opts=options(alpha=1.6), x_warm=x1, u_warm=u)
+    q = torch.zeros((N, nj, 4, H), dtype=torch.float32, device="cuda")
+    x1, _, _ = P.solve(xs, r.q0, r.v0, 40, opts=options(alpha=alpha), state_out=q)
+    x2, rp2, rd2 = P.solve(xs, r.q0, r.v0, 30, opts=options(alpha=alpha), x_warm=x1, state_warm=q)
     torch.cuda.synchronize()
-    O1 = admm.solve_request(r.samples, H, r.dt, r.bounds, r.q0, r.v0, alpha=1.6, iters=40)
+    kw = dict(alpha=alpha, weights=P.weights)
+    O1 = admm.solve_request(r.samples, H, r.dt, r.bounds, r.q0, r.v0, iters=40, **kw)
     np.testing.assert_allclose(x1.cpu().numpy(), O1.x, atol=1e-4)
-    # GPU u layout [N][nj][4][H] (jerk block: entry k holds step k+1's row) -> oracle y = rho u
-    ug = u.cpu().numpy()
-    yg = np.concatenate([ug[:, :, 0, :], ug[:, :, 1, :], ug[:, :, 2, :], ug[:, :, 3, 1:]], axis=2)
-    np.testing.assert_allclose(yg, O1.y / r.rho, atol=2e-4)
-    O2 = admm.solve_request(r.samples, H, r.dt, r.bounds, r.q0, r.v0, alpha=1.6, iters=30,
-                            warm_x=O1.x, warm_y=O1.y)
+    R = admm.block_penalty(H, r.rho, P.weights)
+    np.testing.assert_allclose(q.cpu().numpy(), oracle_state_in_kernel_rows(O1, H, r.v0, alpha, R),
+                               atol=2e-4)
+    O2 = admm.solve_request(r.samples, H, r.dt, r.bounds, r.q0, r.v0, iters=30, warm_x=O1.x,
+                            warm_y=O1.y, warm_z=O1.z, **kw)
     np.testing.assert_allclose(x2.cpu().numpy(), O2.x, atol=1e-4)
     np.testing.assert_allclose(rp2.cpu().numpy(), O2.r_p, atol=1e-4, rtol=1e-3)
 
@@ -204,19 +224,3 @@ def test_block_weights_residual_mode(prec):
         assert np.all(diff <= 0.2 * O.iters + 20)
 
 
-def test_block_weights_dual_state_round_trip():
-    import torch
-    from paper_2608_25666_amd import Projector, options
-    r = W.make_request(27, N=20, H=15, nj=2, dt=0.05, kind="white", sigma=1.0)
-    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights=W_DEF)
-    xs = torch.from_numpy(r.samples).cuda()
-    u = torch.zeros((r.N, r.nj, 4, r.H), dtype=torch.float32, device="cuda")
-    x1, _, _ = P.solve(xs, r.q0, r.v0, 35, opts=options(alpha=1.6), u_out=u)
-    torch.cuda.synchronize()
-    O1 = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, alpha=1.6, iters=35,
-                            weights=P.weights)
-    np.testing.assert_allclose(x1.cpu().numpy(), O1.x, atol=1e-4)
-    ug = u.cpu().numpy()
-    ug = np.concatenate([ug[:, :, 0, :], ug[:, :, 1, :], ug[:, :, 2, :], ug[:, :, 3, 1:]], axis=2)
-    Rrow = admm.block_penalty(r.H, r.rho, P.weights)
-    np.testing.assert_allclose(ug * Rrow, O1.y, atol=1e-3)
