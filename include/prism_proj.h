@@ -189,6 +189,48 @@ typedef struct {
 prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* args,
                                    hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched solve: many requests (each with its own handle, hence its own H,
+ * joint count, dt, bounds and factor) in one persistent launch (Sec. III-D
+ * "Batch parallelism": only the samples and right-hand sides differ between
+ * QPs; here the factors may differ too). Requests are cut into work items of
+ * four tiles (16 samples of one joint each) that share one factor; items are
+ * ordered longest first and pulled by workgroups from an atomic counter.
+ * A batch whose horizons all fall in {17..20, 49..52, 97..100} (chunk sizes
+ * {5, 13, 25}) runs as one launch; other mixes run one launch per chunk-size
+ * class (chunks 2-8, 9-18, 19-32), in order on the same stream.
+ * ------------------------------------------------------------------------- */
+typedef struct prism_batch_s* prism_batch_t;   /* staging buffers for request tables */
+
+typedef struct {
+  prism_proj_t proj;        /* the request's handle (all on one device)             */
+  const float* v_samples;   /* device [N][H][n_joints]                               */
+  int32_t N;                /* samples (0 = nothing to do)                           */
+  int32_t iters;            /* iteration count / cap, >= 0                           */
+  const double* q0;         /* host [n_joints]                                       */
+  const double* v0;         /* host [n_joints]                                       */
+  float* v_out;             /* device [N][H][n_joints]; may alias v_samples          */
+  float* r_primal;          /* device [N][n_joints] or NULL                          */
+  float* r_dual;            /* device [N][n_joints] or NULL                          */
+  int32_t* iters_out;       /* device [N][n_joints] or NULL                          */
+  const float* x_warm;      /* device [N][H][n_joints] or NULL                       */
+  const float* state_warm;  /* device [N][n_joints][4][H] or NULL                    */
+  float* state_out;         /* device [N][n_joints][4][H] or NULL                    */
+} prism_request_t;
+
+/* Create / destroy the staging object (pinned host and device request tables,
+ * grown on demand). One object serves one stream at a time: a call waits until
+ * the previous call's tables have been copied to the device. */
+prism_status_t prism_batch_create(prism_batch_t* out);
+void prism_batch_destroy(prism_batch_t b);
+
+/* Solve every request with the same options (NULL = defaults). All checks of
+ * every request run before anything is enqueued; PRISM_EINVAL / PRISM_EINFEASIBLE
+ * name no request, and nothing is written on error. Each request's outputs are
+ * exactly what prism_proj_solve_ex would produce for it alone. */
+prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_request_t* reqs,
+                                      const prism_options_t* opts, hipStream_t stream);
+
 /* prism_proj_feasibility -- FP64 final check of trajectories (device kernel).
  * For each column writes to viol (device, float64 [N][n_joints][5]) the largest
  * violation of the position (rad), velocity (rad/s), acceleration (rad/s^2)

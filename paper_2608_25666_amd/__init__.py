@@ -8,4 +8,4 @@ not load the library; the first call does, and fails loudly if it is missing.
 from ._lib import (  # noqa: F401
     PREC_BF16, PREC_FP16, PREC_FP32, PrismError, load,
 )
-from .projector import Projector, default_block_weights, factor_host, options  # noqa: F401
+from .projector import Batch, Projector, default_block_weights, factor_host, options  # noqa: F401

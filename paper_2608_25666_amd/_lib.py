@@ -50,6 +50,14 @@ class SolveArgs(C.Structure):
                 ("state_out", C.c_void_p), ("opts", C.POINTER(Options))]
 
 
+class Request(C.Structure):
+    _fields_ = [("proj", C.c_void_p), ("v_samples", C.c_void_p), ("N", C.c_int32),
+                ("iters", C.c_int32), ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
+                ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
+                ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("state_warm", C.c_void_p),
+                ("state_out", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -94,6 +102,10 @@ def load(path: str = LIB_PATH):
         "prism_proj_get_factor": (st, [H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "prism_factor_host": (st, [C.c_int, C.c_double, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "prism_batch_create": (st, [C.POINTER(H)]),
+        "prism_batch_destroy": (None, [H]),
+        "prism_proj_solve_batch": (st, [H, C.c_int, C.POINTER(Request), C.POINTER(Options),
+                                        C.c_void_p]),
         "prism_status_str": (C.c_char_p, [C.c_int]),
         "prism_abi_version": (C.c_int, []),
     }

@@ -32,6 +32,29 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   float* xt_wave = reinterpret_cast<float*>(lds + frag_bytes) + wave * (HQ * 64);
+  TileArgs T;
+  T.xin = A.xin;
+  T.xout = A.xout;
+  T.rp = A.rp;
+  T.rd = A.rd;
+  T.itout = A.itout;
+  T.xw = A.xw;
+  T.uw = A.uw;
+  T.uout = A.uout;
+  T.jp = A.jp;
+  T.N = A.N;
+  T.H = A.H;
+  T.nj = A.nj;
+  T.iters = A.iters;
+  T.check_every = A.check_every;
+  T.tail = A.tail;
+  T.tolmode = A.tolmode;
+  T.rho = A.rho;
+  T.alpha = A.alpha;
+  T.tol = A.tol;
+  T.cV = A.cV;
+  T.cQ = A.cQ;
+  T.cJ = A.cJ;
   for (;;) {
     int t = 0;
     if (lane == 0) t = atomicAdd(A.counter, 1);
@@ -40,7 +63,7 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
     const int j = t % A.nj;
     const int sb = t / A.nj;
     TileSolver<HQ, EXACT, GEMM> ts;
-    ts.run(A, j, sb * kTileCols, kf32, k16, xt_wave);
+    ts.run(T, j, sb * kTileCols, kf32, k16, xt_wave);
   }
 }
 

@@ -342,7 +342,7 @@ struct TileSolver {
     }
   }
 
-  __device__ void run(const SolveKernelArgs& A, int j, int s0, const float* __restrict__ kf32,
+  __device__ void run(const TileArgs& A, int j, int s0, const float* __restrict__ kf32,
                       const void* __restrict__ k16, float* xt_wave) {
     xt_lds = xt_wave;
     lane = threadIdx.x & 63;

@@ -1,0 +1,249 @@
+// Batched solve: many requests with their own factors in one persistent launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "admm_batch.h"
+#include "kernel_args.h"
+#include "prism_internal.h"
+#include "prism_proj.h"
+
+using namespace prism;
+
+struct prism_batch_s {
+  int device = 0;
+  BatchReq* h_reqs = nullptr;        // pinned
+  JointRowParams* h_jp = nullptr;    // pinned
+  BatchReq* d_reqs = nullptr;
+  JointRowParams* d_jp = nullptr;
+  int* d_counters = nullptr;         // one per launch of a call (up to 4)
+  size_t cap_req = 0, cap_jp = 0;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+};
+
+namespace {
+
+__global__ void zero_ints_kernel(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+void release_tables(prism_batch_s* b) {
+  if (b->h_reqs) (void)hipHostFree(b->h_reqs);
+  if (b->h_jp) (void)hipHostFree(b->h_jp);
+  if (b->d_reqs) (void)hipFree(b->d_reqs);
+  if (b->d_jp) (void)hipFree(b->d_jp);
+  b->h_reqs = nullptr;
+  b->h_jp = nullptr;
+  b->d_reqs = nullptr;
+  b->d_jp = nullptr;
+  b->cap_req = b->cap_jp = 0;
+}
+
+prism_status_t reserve(prism_batch_s* b, size_t nreq, size_t njp) {
+  if (nreq <= b->cap_req && njp <= b->cap_jp) return PRISM_OK;
+  release_tables(b);
+  const size_t cr = std::max<size_t>(64, nreq * 2), cj = std::max<size_t>(1024, njp * 2);
+  if (hipHostMalloc((void**)&b->h_reqs, cr * sizeof(BatchReq), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_jp, cj * sizeof(JointRowParams), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&b->d_reqs, cr * sizeof(BatchReq)) != hipSuccess ||
+      hipMalloc((void**)&b->d_jp, cj * sizeof(JointRowParams)) != hipSuccess) {
+    release_tables(b);
+    return PRISM_ENOMEM;
+  }
+  b->cap_req = cr;
+  b->cap_jp = cj;
+  return PRISM_OK;
+}
+
+BatchKernelFn pick_batch_kernel(int set, int precision) {
+  switch (precision) {
+    case PRISM_PREC_FP32: return batch_kernel_f32(set);
+    case PRISM_PREC_BF16: return batch_kernel_bf16(set);
+    case PRISM_PREC_FP16: return batch_kernel_f16(set);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+prism_status_t prism_batch_create(prism_batch_t* out) {
+  if (!out) return PRISM_EINVAL;
+  prism_batch_s* b = new (std::nothrow) prism_batch_s();
+  if (!b) return PRISM_ENOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return PRISM_EDEVICE;
+  }
+  if (hipMalloc((void**)&b->d_counters, 4 * sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+    prism_batch_destroy(b);
+    return PRISM_ENOMEM;
+  }
+  *out = b;
+  return PRISM_OK;
+}
+
+void prism_batch_destroy(prism_batch_t b) {
+  if (!b) return;
+  if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
+  release_tables(b);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->copied) (void)hipEventDestroy(b->copied);
+  delete b;
+}
+
+prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_request_t* reqs,
+                                      const prism_options_t* opts_in, hipStream_t stream) {
+  if (!b || n_req < 0 || (n_req > 0 && !reqs)) return PRISM_EINVAL;
+  prism_options_t opts;
+  if (opts_in) opts = *opts_in;
+  else prism_options_default(&opts);
+  prism_status_t st = validate_options(&opts);
+  if (st != PRISM_OK) return st;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return PRISM_EDEVICE;
+
+  // ---- validate every request before touching anything
+  size_t n_jp = 0;
+  std::vector<int> live;
+  for (int r = 0; r < n_req; ++r) {
+    const prism_request_t& q = reqs[r];
+    const prism_proj_s* p = q.proj;
+    if (!p || q.N < 0 || q.iters < 0 || !q.q0 || !q.v0) return PRISM_EINVAL;
+    if (p->device != b->device) return PRISM_EDEVICE;
+    JointRowParams tmp[kMaxJoints];
+    st = fill_joint_params(p, q.q0, q.v0, tmp);
+    if (st != PRISM_OK) return st;
+    if (q.N == 0) continue;
+    if (!q.v_samples || !q.v_out) return PRISM_EINVAL;
+    if ((long long)q.N * p->H * p->nj > (1ll << 40)) return PRISM_EINVAL;
+    live.push_back(r);
+    n_jp += p->nj;
+  }
+  if (live.empty()) return PRISM_OK;
+
+  // longest work first: chunk^2 * tiles * iterations
+  auto cost = [&](int r) {
+    const prism_proj_s* p = reqs[r].proj;
+    const double tiles = (double)((reqs[r].N + kTileCols - 1) / kTileCols) * p->nj;
+    return (double)p->HQ * p->HQ * tiles * std::max(1, reqs[r].iters);
+  };
+  std::stable_sort(live.begin(), live.end(), [&](int a, int c) { return cost(a) > cost(c); });
+
+  // ---- which launches: one for the {5, 13, 25} set, else one per chunk class
+  bool all_mpc = true;
+  for (int r : live)
+    if (!batch_set_has(0, reqs[r].proj->HQ)) all_mpc = false;
+  std::vector<int> sets;
+  if (all_mpc) sets.push_back(0);
+  else
+    for (int s = 1; s <= 3; ++s)
+      for (int r : live)
+        if (batch_set_has(s, reqs[r].proj->HQ)) {
+          sets.push_back(s);
+          break;
+        }
+
+  if (b->pending) {
+    if (hipEventSynchronize(b->copied) != hipSuccess) return PRISM_EDEVICE;
+    b->pending = false;
+  }
+  st = reserve(b, live.size(), n_jp);
+  if (st != PRISM_OK) return st;
+
+  // ---- build the tables, grouped by launch
+  struct Launch {
+    int set, first, count, items, hq_max, frag_max;
+  };
+  std::vector<Launch> launches;
+  size_t ri = 0, ji = 0;
+  const bool tolmode = opts.tol > 0.0f;
+  for (int s : sets) {
+    Launch L{s, (int)ri, 0, 0, 2, 0};
+    for (int r : live) {
+      const prism_request_t& q = reqs[r];
+      const prism_proj_s* p = q.proj;
+      if (!batch_set_has(s, p->HQ)) continue;
+      BatchReq& B = b->h_reqs[ri++];
+      std::memset(&B, 0, sizeof(B));
+      fill_joint_params(p, q.q0, q.v0, b->h_jp + ji);
+      TileArgs& T = B.t;
+      T.xin = q.v_samples;
+      T.xout = q.v_out;
+      T.rp = q.r_primal;
+      T.rd = q.r_dual;
+      T.itout = q.iters_out;
+      T.xw = q.x_warm;
+      T.uw = q.state_warm;
+      T.uout = q.state_out;
+      T.jp = b->d_jp + ji;
+      T.N = q.N;
+      T.H = p->H;
+      T.nj = p->nj;
+      T.iters = q.iters;
+      T.check_every = opts.check_every;
+      T.tolmode = tolmode ? 1 : 0;
+      T.tail = (opts.precision == PRISM_PREC_FP32) ? 0
+                                                   : std::min(opts.fp32_tail, tolmode ? opts.fp32_tail : q.iters);
+      T.rho = (float)(p->rho * p->w[2]);
+      T.alpha = opts.alpha;
+      T.tol = opts.tol;
+      T.cV = (float)(p->w[0] / p->w[2]);
+      T.cQ = (float)(p->w[1] / p->w[2]);
+      T.cJ = (float)(p->w[3] / p->w[2]);
+      B.frag = (opts.precision == PRISM_PREC_FP16) ? p->frag_f16 : p->frag_bf16;
+      B.HQ = p->HQ;
+      B.frag_f32_bytes = p->f32_bytes;
+      B.frag_16_bytes = p->b16_bytes;
+      B.tiles = ((q.N + kTileCols - 1) / kTileCols) * p->nj;
+      B.items = (B.tiles + kWaves - 1) / kWaves;
+      B.item_begin = L.items;
+      L.items += B.items;
+      L.count++;
+      L.hq_max = std::max(L.hq_max, p->HQ);
+      L.frag_max = std::max(L.frag_max, solve_frag_bytes(p, opts.precision));
+      ji += p->nj;
+    }
+    launches.push_back(L);
+  }
+
+  // ---- upload tables, clear counters, launch
+  if (hipMemcpyAsync(b->d_jp, b->h_jp, ji * sizeof(JointRowParams), hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b->d_reqs, b->h_reqs, ri * sizeof(BatchReq), hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      hipEventRecord(b->copied, stream) != hipSuccess)
+    return PRISM_EDEVICE;
+  b->pending = true;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, b->d_counters, 4);
+  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const Launch& L = launches[li];
+    BatchKernelFn fn = pick_batch_kernel(L.set, opts.precision);
+    if (!fn) return PRISM_EUNSUPPORTED;
+    BatchKernelArgs A{};
+    A.reqs = b->d_reqs + L.first;
+    A.n_req = L.count;
+    A.n_items = L.items;
+    A.counter = b->d_counters + li;
+    A.xt_offset = L.frag_max;
+    A.hq_max = L.hq_max;
+    const int lds = L.frag_max + kWaves * L.hq_max * 64 * (int)sizeof(float);
+    const int bpc = kernel_blocks_per_cu((const void*)fn, lds);
+    const int grid = (int)std::max(1ll, std::min((long long)L.items, (long long)bpc * device_cus()));
+    void* params[] = {&A};
+    if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
+      return PRISM_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  }
+  return PRISM_OK;
+}
+
+}  // extern "C"

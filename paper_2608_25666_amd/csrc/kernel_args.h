@@ -24,6 +24,21 @@ struct JointRowParams {
   float pad[3];
 };
 
+// What one tile needs to know about its request (single solve or batch entry).
+struct TileArgs {
+  const float* xin;
+  float* xout;
+  float* rp;
+  float* rd;
+  int* itout;
+  const float* xw;
+  const float* uw;
+  float* uout;
+  const JointRowParams* jp;   // n_joints entries
+  int N, H, nj, iters, check_every, tail, tolmode;
+  float rho, alpha, tol, cV, cQ, cJ;
+};
+
 struct SolveKernelArgs {
   const float* xin;      // [N][H][nj]
   float* xout;           // [N][H][nj]
@@ -41,6 +56,27 @@ struct SolveKernelArgs {
   float cV, cQ, cJ;               // block weights relative to the acceleration block
   int frag_f32_bytes, frag_16_bytes;
   JointRowParams jp[kMaxJoints];
+};
+
+// One request of a batched launch (device memory). Its tiles are grouped in
+// work items of kWaves tiles that share the request's factor.
+struct BatchReq {
+  TileArgs t;
+  const void* frag;          // FP32 fragments, then 16-bit fragments
+  int HQ;
+  int frag_f32_bytes, frag_16_bytes;
+  int tiles;                 // ceil(N / 16) * n_joints
+  int item_begin;            // first global work item of this request
+  int items;                 // ceil(tiles / kWaves)
+};
+
+struct BatchKernelArgs {
+  const BatchReq* reqs;      // sorted so that item_begin is increasing
+  int n_req;
+  int n_items;
+  int* counter;              // work-item counter, zero at launch
+  int xt_offset;             // LDS byte offset of the per-wave sample copies
+  int hq_max;                // largest chunk size in this launch
 };
 
 struct FeasKernelArgs {

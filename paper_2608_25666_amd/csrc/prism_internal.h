@@ -36,6 +36,10 @@ prism_status_t fill_joint_params(const prism_proj_s* p, const double* q0, const 
                                  JointRowParams* jp);
 SolveKernelFn pick_kernel(int HQ, bool exact, int precision);
 int solve_lds_bytes(const prism_proj_s* p, int precision);
+int solve_frag_bytes(const prism_proj_s* p, int precision);
+prism_status_t validate_options(const prism_options_t* o);
+int kernel_blocks_per_cu(const void* fn, int lds_bytes);   // occupancy, cached per (kernel, LDS)
+int device_cus();
 hipError_t launch_feasibility(const FeasKernelArgs& a, hipStream_t stream);
 
 }  // namespace prism

@@ -65,6 +65,10 @@ int blocks_per_cu(const void* fn, int lds) {
 
 __global__ void zero_counter_kernel(int* c) { *c = 0; }
 
+}  // namespace
+
+namespace prism {
+
 prism_status_t validate_options(const prism_options_t* o) {
   if (!o) return PRISM_EINVAL;
   if (o->precision < PRISM_PREC_FP32 || o->precision > PRISM_PREC_FP16) return PRISM_EINVAL;
@@ -77,7 +81,10 @@ prism_status_t validate_options(const prism_options_t* o) {
   return PRISM_OK;
 }
 
-}  // namespace
+int kernel_blocks_per_cu(const void* fn, int lds_bytes) { return blocks_per_cu(fn, lds_bytes); }
+int device_cus() { return num_cus(); }
+
+}  // namespace prism
 
 // ---------------------------------------------------------------------------
 // Internal helpers shared with the batch and server front ends
@@ -123,9 +130,12 @@ SolveKernelFn pick_kernel(int HQ, bool exact, int precision) {
   }
 }
 
+int solve_frag_bytes(const prism_proj_s* p, int precision) {
+  return p->f32_bytes + (precision == PRISM_PREC_FP32 ? 0 : p->b16_bytes);
+}
+
 int solve_lds_bytes(const prism_proj_s* p, int precision) {
-  const int frag = p->f32_bytes + (precision == PRISM_PREC_FP32 ? 0 : p->b16_bytes);
-  return frag + kWaves * p->HQ * 64 * (int)sizeof(float);
+  return solve_frag_bytes(p, precision) + kWaves * p->HQ * 64 * (int)sizeof(float);
 }
 
 }  // namespace prism

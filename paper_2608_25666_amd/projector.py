@@ -162,3 +162,68 @@ def factor_host(H: int, rho: float, weights=None):
                                       k.ctypes.data_as(C.POINTER(C.c_double))),
             "prism_factor_host")
     return K, k
+
+
+class Batch:
+    """Staging object for prism_proj_solve_batch: many requests, one persistent launch.
+
+    solve() takes a list of dicts with keys proj (a Projector), samples, q0, v0,
+    iters and optionally out, r_primal, r_dual, iters_out, x_warm, state_warm,
+    state_out (tensors as for Projector.solve). Missing out / r_primal / r_dual
+    are allocated. Returns the list of (v_out, r_primal, r_dual).
+    """
+
+    def __init__(self):
+        h = C.c_void_p()
+        L.check(L.lib().prism_batch_create(C.byref(h)), "prism_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().prism_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, requests, opts: Optional[L.Options] = None, stream=None):
+        import torch
+        n = len(requests)
+        arr = (L.Request * max(n, 1))()
+        keep, outs = [], []
+        for i, r in enumerate(requests):
+            P = r["proj"]
+            x = r["samples"]
+            N = int(x.shape[0])
+            assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+            assert tuple(x.shape[1:]) == (P.H, P.nj)
+            out = r.get("out")
+            out = torch.empty_like(x) if out is None else out
+            rp = r.get("r_primal")
+            rp = torch.empty((N, P.nj), dtype=torch.float32, device=x.device) if rp is None else rp
+            rd = r.get("r_dual")
+            rd = torch.empty((N, P.nj), dtype=torch.float32, device=x.device) if rd is None else rd
+            q0a = L.dbl_array(np.broadcast_to(np.asarray(r["q0"], dtype=np.float64), (P.nj,)))
+            v0a = L.dbl_array(np.broadcast_to(np.asarray(r["v0"], dtype=np.float64), (P.nj,)))
+            keep += [q0a, v0a]
+            a = arr[i]
+            a.proj = P.handle.value
+            a.v_samples = x.data_ptr()
+            a.N = N
+            a.iters = int(r["iters"])
+            a.q0 = C.cast(q0a, C.POINTER(C.c_double))
+            a.v0 = C.cast(v0a, C.POINTER(C.c_double))
+            a.v_out = out.data_ptr()
+            a.r_primal = rp.data_ptr()
+            a.r_dual = rd.data_ptr()
+            for f in ("iters_out", "x_warm", "state_warm", "state_out"):
+                t = r.get(f)
+                setattr(a, f, None if t is None else t.data_ptr())
+            outs.append((out, rp, rd))
+        po = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
+        L.check(L.lib().prism_proj_solve_batch(self._h, n, arr, po, _stream(stream)),
+                "prism_proj_solve_batch")
+        return outs

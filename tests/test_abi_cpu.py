@@ -122,3 +122,10 @@ def test_null_handle_calls_are_rejected():
     assert lib.prism_proj_horizon(None) == -1
     lib.prism_proj_destroy(None)
     assert lib.prism_factor_host(1, 1.0, None, None, None) == L.PRISM_EINVAL
+
+
+def test_batch_null_arguments_rejected():
+    L, lib = _lib()
+    assert lib.prism_batch_create(None) == L.PRISM_EINVAL
+    assert lib.prism_proj_solve_batch(None, 0, None, None, None) == L.PRISM_EINVAL
+    lib.prism_batch_destroy(None)

@@ -1,0 +1,134 @@
+"""Uneven batch in one persistent launch (prism_proj_solve_batch).
+
+Each request keeps its own horizon, joint count, dt, bounds and factor. The
+batched result of a request must equal what its own prism_proj_solve_ex call
+gives (same tile code, same arithmetic order), and match the FP64 oracle at
+the FP32 bar (1e-4 rad/s max-abs) on sampled requests.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import admm
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_mix(seed, h_choices=(20, 50, 100), n_choices=(16, 37, 64), n_requests=10):
+    return W.config4_requests(seed=seed, n_requests=n_requests, n_choices=n_choices,
+                              h_choices=h_choices, iters=100)
+
+
+def _batch_and_single(reqs, iters, opts, weights="default", with_iters=False):
+    import torch
+    from paper_2608_25666_amd import Batch, Projector
+    projs = [Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights=weights) for r in reqs]
+    xs = [torch.from_numpy(np.ascontiguousarray(r.samples)).cuda() for r in reqs]
+    its = [torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda") for r in reqs]
+    B = Batch()
+    outs = B.solve([dict(proj=P, samples=x, q0=r.q0, v0=r.v0, iters=iters,
+                         iters_out=it if with_iters else None)
+                    for P, x, r, it in zip(projs, xs, reqs, its)], opts=opts)
+    torch.cuda.synchronize()
+    batched = [(o.cpu().numpy(), rp.cpu().numpy(), rd.cpu().numpy(), it.cpu().numpy())
+               for (o, rp, rd), it in zip(outs, its)]
+    single = []
+    for P, x, r in zip(projs, xs, reqs):
+        it = torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda")
+        o, rp, rd = P.solve(x, r.q0, r.v0, iters, opts=opts, iters_out=it if with_iters else None)
+        torch.cuda.synchronize()
+        single.append((o.cpu().numpy(), rp.cpu().numpy(), rd.cpu().numpy(), it.cpu().numpy()))
+    ws = [P.weights for P in projs]
+    B.close()
+    for P in projs:
+        P.close()
+    return batched, single, ws
+
+
+def _assert_same(batched, single, exact=True):
+    for b, s in zip(batched, single):
+        for u, v in zip(b, s):
+            if exact:
+                np.testing.assert_array_equal(u, v)
+            else:
+                np.testing.assert_allclose(u, v, atol=2e-6, rtol=0)
+
+
+def test_batch_mpc_set_equals_single_solves_and_oracle():
+    """Horizons 20/50/100 (one launch), sample counts with ragged tails, 6 or 12 joints."""
+    from paper_2608_25666_amd import options
+    reqs = _small_mix(3)
+    assert len({r.H for r in reqs}) >= 2
+    batched, single, ws = _batch_and_single(reqs, 100, options(alpha=1.6))
+    _assert_same(batched, single)
+    worst = 0.0
+    for r, b, w in list(zip(reqs, batched, ws))[:4]:
+        pick = np.unique(np.r_[0, 1, r.N - 1])
+        O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=100,
+                               alpha=1.6, weights=w)
+        err = np.abs(b[0][pick] - O.x).max()
+        worst = max(worst, err)
+        np.testing.assert_allclose(b[1][pick], O.r_p, atol=1e-4, rtol=1e-3)
+        np.testing.assert_allclose(b[2][pick], O.r_d, atol=1e-4, rtol=1e-3)
+    print(f"batch vs oracle worst max-abs {worst:.3e}")
+    assert worst <= 1e-4
+
+
+def test_batch_mixed_chunk_classes():
+    """Horizons outside {20,50,100}: one launch per chunk class, still per-request exact."""
+    from paper_2608_25666_amd import options
+    reqs = _small_mix(4, h_choices=(2, 7, 33, 64, 128), n_choices=(5, 16, 40), n_requests=9)
+    batched, single, ws = _batch_and_single(reqs, 60, options(alpha=1.6))
+    _assert_same(batched, single)
+    r, b, w = reqs[0], batched[0], ws[0]
+    O = admm.solve_request(r.samples[:3], r.H, r.dt, r.bounds, r.q0, r.v0, iters=60,
+                           alpha=1.6, weights=w)
+    assert np.abs(b[0][:3] - O.x).max() <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_batch_reduced_precision_equals_single(prec):
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
+    p = PREC_BF16 if prec == "bf16" else PREC_FP16
+    reqs = _small_mix(5, n_requests=6)
+    batched, single, _ = _batch_and_single(reqs, 100, options(precision=p, fp32_tail=10, alpha=1.6))
+    _assert_same(batched, single)
+
+
+def test_batch_residual_mode_iteration_counts():
+    """Residual-driven stopping per group of 16 samples inside the batch."""
+    from paper_2608_25666_amd import options
+    reqs = _small_mix(6, n_requests=6)
+    batched, single, _ = _batch_and_single(reqs, 3000, options(alpha=1.6, tol=1e-3), with_iters=True)
+    _assert_same(batched, single)
+    for b in batched:
+        assert np.all(np.maximum(b[1], b[2]) <= 1e-3)
+
+
+def test_batch_empty_and_invalid_requests():
+    import torch
+    from paper_2608_25666_amd import Batch, PrismError, Projector
+    r = W.make_request(7, N=20, H=20, nj=2, dt=0.05, kind="white")
+    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+    x = torch.from_numpy(np.ascontiguousarray(r.samples)).cuda()
+    B = Batch()
+    assert B.solve([]) == []
+    empty = torch.zeros((0, r.H, r.nj), dtype=torch.float32, device="cuda")
+    out = torch.full_like(x, 7.0)
+    B.solve([dict(proj=P, samples=empty, q0=r.q0, v0=r.v0, iters=50),
+             dict(proj=P, samples=x, q0=r.q0, v0=r.v0, iters=50, out=out)])
+    torch.cuda.synchronize()
+    ref, _, _ = P.solve(x, r.q0, r.v0, 50)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref.cpu().numpy())
+    # a request whose boundary state is infeasible rejects the whole call, nothing written
+    out2 = torch.full_like(x, 7.0)
+    bad_v0 = np.full(r.nj, 100.0)
+    with pytest.raises(PrismError):
+        B.solve([dict(proj=P, samples=x, q0=r.q0, v0=r.v0, iters=50, out=out2),
+                 dict(proj=P, samples=x, q0=r.q0, v0=bad_v0, iters=50)])
+    torch.cuda.synchronize()
+    assert np.all(out2.cpu().numpy() == 7.0)
+    B.close()
+    P.close()
