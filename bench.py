@@ -14,7 +14,13 @@ solve kernel (timed live with HIP events on the solve's stream) and the FP64
 oracle timed on the host cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16|fp16]
-                    [--alpha A] [--no-cpu-baseline] [--iters-cap C]
+                    [--alpha A] [--no-cpu-baseline] [--iters-cap C] [--workload cfg2|cfg3|cfg4]
+
+--workload cfg3: 12 joints, N = 8192, H = 100 (same generator).
+--workload cfg4: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
+6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
+prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
+--precision one).
 """
 
 from __future__ import annotations
@@ -76,32 +82,177 @@ def parse():
                     help="time a fixed iteration count instead of the residual target")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
-    ap.add_argument("--cpu-sample", type=int, default=32, help="samples (all joints) for the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (3 times): its "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic figures")
     return ap.parse_args()
 
 
+def _oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    except Exception:
+        return 1
+
+
 def cpu_baseline(req, tol, check_every, cap, alpha, nsamp, weights):
     """The FP64 oracle on the first nsamp samples (all joints), timed on the host."""
     from oracle import admm
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
     S = req.samples[:nsamp]
+    chunk = 32
+    itmax = 0
     t0 = time.perf_counter()
-    O = admm.solve_request(S, req.H, req.dt, req.bounds, req.q0, req.v0, rho=req.rho,
-                           alpha=alpha, iters=cap, tol=tol, check_every=check_every,
-                           weights=weights)
+    for c0 in range(0, S.shape[0], chunk):
+        O = admm.solve_request(S[c0:c0 + chunk], req.H, req.dt, req.bounds, req.q0, req.v0,
+                               rho=req.rho, alpha=alpha, iters=cap, tol=tol,
+                               check_every=check_every, weights=weights)
+        itmax = max(itmax, int(O.iters.max()))
     dt = time.perf_counter() - t0
-    return {"value": nsamp / dt, "unit": "trajectories/s", "cores": int(threads),
+    return {"value": S.shape[0] / dt, "unit": "trajectories/s", "cores": _oracle_threads(),
             "kind": "oracle",
-            "sample": f"first {nsamp} samples x {req.nj} joints of the benchmark batch, FP64 "
-                      f"NumPy oracle to residual <= {tol:g} (check every {check_every}); "
-                      f"{dt:.1f} s; max group iterations {int(O.iters.max())}"}
+            "sample": f"first {S.shape[0]} samples x {req.nj} joints of the benchmark batch "
+                      f"(oracle called on {chunk} samples at a time), FP64 NumPy oracle to "
+                      f"residual <= {tol:g} (check every {check_every}); {dt:.1f} s; max group "
+                      f"iterations {itmax}"}
+
+
+def cpu_baseline_batch(reqs, tol, check_every, cap, alpha, per_req, weights_of):
+    """The FP64 oracle on the first per_req samples of every request, timed on the host."""
+    from oracle import admm
+    n = 0
+    t0 = time.perf_counter()
+    for r in reqs:
+        S = r.samples[:per_req]
+        admm.solve_request(S, r.H, r.dt, r.bounds, r.q0, r.v0, rho=r.rho, alpha=alpha, iters=cap,
+                           tol=tol, check_every=check_every, weights=weights_of(r))
+        n += S.shape[0]
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "trajectories/s", "cores": _oracle_threads(), "kind": "oracle",
+            "sample": f"first {per_req} samples of each of the {len(reqs)} requests ({n} "
+                      f"trajectories), FP64 NumPy oracle to residual <= {tol:g}; {dt:.1f} s"}
+
+
+def roofline(col_iters_by_H, kern_s, prec_is_f32):
+    """Roofline object for the solve kernel: algorithmic VALU and MFMA work of the
+    column-iterations actually run, over the kernel's measured time."""
+    valu = sum(valu_ops_per_col_iter(H) * c for H, c in col_iters_by_H.items())
+    mflop = sum(mfma_flops_per_col_iter(H) * c for H, c in col_iters_by_H.items())
+    peak_mfma = PEAK_MFMA_F32_TFLOPS if prec_is_f32 else PEAK_MFMA_B16_TFLOPS
+    t_valu = valu / (PEAK_VALU_TOPS * 1e12)
+    t_mfma = mflop / (peak_mfma * 1e12)
+    if t_valu >= t_mfma:
+        ach = valu / kern_s / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_VALU_TOPS}
+    else:
+        ach = mflop / kern_s / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": peak_mfma, "unit": "TFLOP/s",
+                "frac": ach / peak_mfma}
+    roof["traffic"] = None
+    roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
+    return roof
+
+
+def _timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        fn()
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([s.elapsed_time(e) for s, e in ev])
+
+
+def run_batch(a):
+    """Uneven batch: 64 requests, one prism_proj_solve_batch call per step."""
+    import torch
+    import workloads as W
+    from paper_2608_25666_amd import Batch, Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
+    reqs = W.config4_requests()
+    dev = torch.device("cuda:0")
+    handles = {}
+    for r in reqs:
+        key = (r.H, r.nj, r.dt)
+        if key not in handles:
+            handles[key] = Projector(r.H, r.nj, r.dt, r.bounds, r.rho,
+                                     weights=None if a.weights == "unit" else "default")
+    xs = [torch.from_numpy(r.samples).to(dev) for r in reqs]
+    outs = [torch.empty_like(x) for x in xs]
+    rps = [torch.empty((r.N, r.nj), dtype=torch.float32, device=dev) for r in reqs]
+    rds = [torch.empty_like(t) for t in rps]
+    its = [torch.empty((r.N, r.nj), dtype=torch.int32, device=dev) for r in reqs]
+    B = Batch()
+    stream = torch.cuda.current_stream()
+    fixed = a.fixed_iters > 0
+    n_it = a.fixed_iters if fixed else a.iters_cap
+    total_traj = sum(r.N for r in reqs)
+
+    def measure(prec):
+        opts = options(precision=prec, alpha=a.alpha, tol=0.0 if fixed else a.tol,
+                       check_every=a.check_every, fp32_tail=a.fp32_tail)
+        items = [dict(proj=handles[(r.H, r.nj, r.dt)], samples=x, q0=r.q0, v0=r.v0, iters=n_it,
+                      out=o, r_primal=rp, r_dual=rd, iters_out=it)
+                 for r, x, o, rp, rd, it in zip(reqs, xs, outs, rps, rds, its)]
+        wall, per = _timed(lambda: B.solve(items, opts=opts, stream=stream), a.steps, a.warmup,
+                           stream)
+        col_iters = {}
+        worst, conv, itmax, itsum, ncol = 0.0, 0, 0, 0.0, 0
+        for r, rp, rd, it in zip(reqs, rps, rds, its):
+            i = it.cpu().numpy()
+            res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+            col_iters[r.H] = col_iters.get(r.H, 0.0) + float(i.sum())
+            conv += int((res <= a.tol).sum())
+            ncol += res.size
+            itmax = max(itmax, int(i.max()))
+            itsum += float(i.sum())
+        ms = wall * 1e3 / a.steps
+        roof = roofline(col_iters, float(per.mean()) * 1e-3, prec == PREC_FP32)
+        return {"value": total_traj / (ms * 1e-3), "ms_per_step": ms,
+                "latency_ms": {"p50": float(np.percentile(per, 50)),
+                               "p99": float(np.percentile(per, 99))},
+                "iterations": {"max": itmax, "mean": itsum / ncol, "converged_frac": conv / ncol},
+                "roofline": roof}
+
+    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
+    m = measure(main_prec)
+    o = measure(other)
+    shapes = sorted({(r.H, r.nj, r.dt) for r in reqs})
+    line = {
+        "metric": ("projected trajectories/sec at residual <=1e-3" if not fixed else
+                   f"projected trajectories/sec at {a.fixed_iters} iterations"),
+        "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if main_prec == PREC_FP32 else ("bf16+f32" if main_prec == PREC_BF16
+                                                         else "f16+f32"),
+        "data": "synthetic",
+        "config": {"workload": "uneven batch in one persistent launch: 64 requests, H in "
+                               "{20,50,100}, N in {128,512,2048,4096}, 6 or 12 joints, dt in "
+                               "{0.02,0.05}, own factor each, smooth 3-sinusoid + N(0,0.5^2) "
+                               "samples, residual <= 1e-3",
+                   "requests": len(reqs), "trajectories": total_traj,
+                   "distinct_factors": len(shapes), "alpha": a.alpha, "precision": a.precision,
+                   "tol": a.tol, "check_every": a.check_every, "iters_cap": a.iters_cap},
+        "latency_ms": m["latency_ms"], "iterations": m["iterations"], "roofline": m["roofline"],
+        "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(
+            reqs, a.tol, a.check_every, a.iters_cap, a.alpha, max(1, a.cpu_sample // 64),
+            lambda r: handles[(r.H, r.nj, r.dt)].weights)
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -115,7 +266,6 @@ def main():
     import workloads as W
     from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
 
-    prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     if a.copy_calibrate_mb > 0:
         nbytes = a.copy_calibrate_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -124,7 +274,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    req = W.config2(N=a.N)
+    if a.workload == "cfg4":
+        return run_batch(a)
+    prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    req = W.config3() if a.workload == "cfg3" else W.config2(N=a.N)
     dev = torch.device("cuda:0")
     P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho,
                   weights=None if a.weights == "unit" else "default")
@@ -218,8 +371,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == PREC_FP32 else ("bf16+f32" if prec == PREC_BF16 else "f16+f32"),
         "data": "synthetic",
-        "config": {"workload": "projection QP, 12 joints, N=2048, H=50, dt=0.02, rho=1, smooth "
-                               "3-sinusoid + N(0,0.5^2) samples, residual <= 1e-3",
+        "config": {"workload": f"projection QP, 12 joints, N={req.N}, H={H}, dt={req.dt}, rho=1, "
+                               "smooth 3-sinusoid + N(0,0.5^2) samples, residual <= 1e-3",
                    "N": req.N, "H": H, "joints": req.nj, "dt": req.dt, "rho": req.rho,
                    "alpha": a.alpha, "block_weights": P.weights or (1.0, 1.0, 1.0, 1.0),
                    "precision": a.precision, "tol": a.tol,

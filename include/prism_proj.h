@@ -82,8 +82,10 @@ typedef enum {
 typedef struct {
   int32_t precision;    /* prism_precision_t                                         */
   int32_t fp32_tail;    /* reduced forms: with tol <= 0 the last fp32_tail of the
-                           iterations use the FP32 GEMM; with tol > 0, fp32_tail
-                           FP32 iterations follow convergence                        */
+                           iterations use the FP32 GEMM. With tol > 0 the reduced
+                           GEMM runs until a group meets tol; then (if fp32_tail >
+                           0) fp32_tail FP32 iterations follow and the group stops
+                           at the next check that meets tol, staying in FP32       */
   float alpha;          /* over-relaxation in (0, 2); 1 = plain ADMM                 */
   float tol;            /* <= 0: run exactly `iters` iterations. > 0: each group of
                            16 samples of one joint stops at the first check point

@@ -34,6 +34,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <type_traits>
 
 #include "kernel_args.h"
@@ -424,23 +426,30 @@ struct TileSolver {
     const bool reduced = GEMM != GEMM_F32;
     const int iters = A.iters;
     const int ce = A.check_every;
-    const int f32_from = (!reduced || tolmode) ? 0 : iters - A.tail;
+    // Fixed count: the last `tail` iterations run the FP32 GEMM. Residual-driven:
+    // the reduced GEMM runs until the group meets the tolerance, then `tail` FP32
+    // iterations follow and the group stops at the next check that still meets it
+    // (further FP32 iterations, checked every check_every, if it does not).
+    const int f32_from = !reduced ? 0 : (tolmode ? INT_MAX : iters - A.tail);
+    bool f32p = !reduced;
     int it = 0;
-    int tail_left = -1;          // >= 0 while running FP32 iterations after convergence
+    int tail_left = -1;          // FP32 iterations left in the tail after convergence
     for (;;) {
       const bool chk = (it == iters) || (tolmode && (it % ce) == 0) || tail_left == 0;
       if (chk) row_update<true>();
       else row_update<false>();
-      if (tail_left == 0) break;
-      if (chk && tolmode && tail_left < 0) {
+      if (chk && tolmode) {
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
         if (wave_max(r) <= A.tol) {
-          if (!reduced || A.tail <= 0) break;
+          if (f32p || A.tail <= 0) break;
+          f32p = true;
           tail_left = A.tail;
+        } else if (tail_left == 0) {
+          tail_left = -1;
         }
       }
-      if (it == iters && tail_left < 0) break;
-      if (!reduced || it >= f32_from || tail_left > 0) gemm_f32(kf32);
+      if (it == iters) break;
+      if (f32p || it >= f32_from) gemm_f32(kf32);
       else gemm_16(k16);
       ++it;
       if (tail_left > 0) --tail_left;

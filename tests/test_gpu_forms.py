@@ -108,8 +108,12 @@ def test_fp32_tail_after_convergence():
     r = W.make_request(23, N=32, H=20, nj=2, dt=0.05, kind="white", sigma=1.0)
     x, rp, rd, it = _run(r, 5000, options(precision=PREC_BF16, tol=1e-3, fp32_tail=10))
     x0, rp0, rd0, it0 = _run(r, 5000, options(precision=PREC_BF16, tol=1e-3))
-    assert np.all(it == it0 + 10)
-    assert np.all(np.maximum(rp, rd) <= 1e-3 * 1.5)
+    # the BF16 phase is identical in both runs; the tail adds 10 FP32 iterations and the
+    # group stops at the first check after it that meets the tolerance
+    extra = it - it0
+    assert np.all(extra >= 10) and np.all((extra - 10) % 10 == 0)
+    assert np.all(np.maximum(rp, rd) <= 1e-3)
+    assert np.all(np.maximum(rp0, rd0) <= 1e-3)
 
 
 def oracle_state_in_kernel_rows(O, H, v0, alpha, R):
@@ -224,3 +228,24 @@ def test_block_weights_residual_mode(prec):
         assert np.all(diff <= 0.2 * O.iters + 20)
 
 
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_reduced_form_residual_mode_reaches_tolerance(prec):
+    """Residual-driven runs with the reduced GEMM: every group ends at residual <= tol, with
+    iteration counts near the FP32 form's, and x near the oracle's at the same tolerance
+    (both sit within the residual tolerance of the same projection)."""
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
+    p = PREC_BF16 if prec == "bf16" else PREC_FP16
+    r = W.make_request(27, N=48, H=50, nj=3, dt=0.02, kind="smooth")
+    kw = dict(alpha=1.6, tol=1e-3)
+    x, rp, rd, it, w = _run_w(r, 20000, options(precision=p, fp32_tail=10, **kw), W_DEF)
+    xf, rpf, rdf, itf, _ = _run_w(r, 20000, options(**kw), W_DEF)
+    assert np.all(np.maximum(rp, rd) <= 1e-3)
+    O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=20000, weights=w,
+                           check_every=10, **kw)
+    err = np.abs(x - O.x).max()
+    print(f"{prec} residual mode: iters {it.mean():.0f} (fp32 {itf.mean():.0f}, oracle "
+          f"{O.iters.mean():.0f}); max-abs vs oracle {err:.3e}, fp32 form {np.abs(xf - O.x).max():.3e}")
+    assert it.mean() <= 1.3 * itf.mean() + 20
+    assert err <= 5e-3
