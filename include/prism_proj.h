@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define PRISM_PROJ_ABI_VERSION 1
+#define PRISM_PROJ_ABI_VERSION 2
 #define PRISM_MAX_H 128          /* horizon limit: the x-update inverse is staged on-chip */
 #define PRISM_MAX_JOINTS 64
 
@@ -169,7 +169,19 @@ prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N,
  *                0 of the jerk block is unused (jerk rows are steps 2..H).
  *                NULL = cold start (previous slack C x0, multiplier 0).
  *   state_out:   device float32 [N][n_joints][4][H] or NULL: final q, same
- *                layout, for warm-starting the next MPC step after a shift.
+ *                layout, for warm-starting the next MPC step.
+ *   warm_shift:  0 or 1. With 1 the warm start is advanced by one MPC step (time
+ *                moves by dt): step k takes the previous step k + 1, the last
+ *                step repeating, for the iterate x_warm and, row block by row
+ *                block, for the scaled multiplier and the slack's deviation from
+ *                C x_warm (both held in state_warm); the slack is then rebuilt
+ *                on the shifted iterate: q' = (1 - alpha) C x' +
+ *                shift(q - (1 - alpha) C x_warm), where x_warm's first step is
+ *                the previous boundary velocity. The acceleration row of step 1
+ *                (fixed by x_1 = v0) restarts at zero. Requires x_warm when
+ *                state_warm is given (PRISM_EINVAL otherwise). x_warm may alias
+ *                v_out and state_warm may alias state_out (each column is read
+ *                before it is written).
  * The first pass is a relaxed slack/multiplier step t = alpha C x0 + q0,
  * z0 = clip(t), u0 = t - z0, with q0 = state_warm or (1 - alpha) C x0. */
 typedef struct {
@@ -186,6 +198,7 @@ typedef struct {
   const float* state_warm;
   float* state_out;
   const prism_options_t* opts;
+  int32_t warm_shift;
 } prism_solve_args_t;
 
 prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* args,
@@ -200,7 +213,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * ordered longest first and pulled by workgroups from an atomic counter.
  * A batch whose horizons all fall in {17..20, 49..52, 97..100} (chunk sizes
  * {5, 13, 25}) runs as one launch; other mixes run one launch per chunk-size
- * class (chunks 2-8, 9-18, 19-32), in order on the same stream.
+ * class (chunks 2-8, 9-16, 17-32), in order on the same stream.
  * ------------------------------------------------------------------------- */
 typedef struct prism_batch_s* prism_batch_t;   /* staging buffers for request tables */
 
@@ -218,6 +231,7 @@ typedef struct {
   const float* x_warm;      /* device [N][H][n_joints] or NULL                       */
   const float* state_warm;  /* device [N][n_joints][4][H] or NULL                    */
   float* state_out;         /* device [N][n_joints][4][H] or NULL                    */
+  int32_t warm_shift;       /* 0 or 1, as in prism_solve_args_t                      */
 } prism_request_t;
 
 /* Create / destroy the staging object (pinned host and device request tables,

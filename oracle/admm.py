@@ -222,6 +222,36 @@ def shift_state(x: np.ndarray, y: np.ndarray, H: int):
     return xs, shift_rows(y, H)
 
 
+def advance_warm_start(x: np.ndarray, y: np.ndarray, z: np.ndarray, H: int, v0_new):
+    """Warm start of the next MPC step from a previous result (the paper does not
+    define one; this is the library's reading, stated here in full).
+
+    Time advances by dt, so step k of the new problem takes step k + 1 of the old
+    one, the last step repeating, block by block for the rows:
+    * the iterate: x'_k = x_{k+1}, x'_H = x_H, and x'_1 = v0_new;
+    * the multiplier y and the slack's deviation from the constraint values,
+      d = z - C x (zero at convergence), are advanced the same way;
+    * the slack is rebuilt on the new iterate, z' = C x' + d'.
+    The acceleration row of step 1 is fixed by x_1 = v0 and restarts with zero
+    multiplier and zero deviation. C = [I; L; D1; D2] in velocity units; the
+    boundary values sit in the row bounds, so they need no handling here.
+
+    x: [N][H][nj]; y, z: [N][nj][4H-1]; v0_new: [nj]. Returns (x', y', z').
+    """
+    C = np.vstack([np.eye(H), problem.L_matrix(H), problem.D1_matrix(H), problem.D2_matrix(H)])
+    A0 = 2 * H                                   # row: acceleration of step 1
+    x = np.asarray(x, dtype=np.float64)
+    xs = np.concatenate([x[:, 1:, :], x[:, -1:, :]], axis=1)
+    xs[:, 0, :] = np.asarray(v0_new, dtype=np.float64)[None, :]
+    d = np.asarray(z, dtype=np.float64) - np.einsum("rh,nhj->njr", C, x)
+    ys = shift_rows(np.asarray(y, dtype=np.float64), H)
+    ds = shift_rows(d, H)
+    ys[:, :, A0] = 0.0
+    ds[:, :, A0] = 0.0
+    zs = np.einsum("rh,nhj->njr", C, xs) + ds
+    return xs, ys, zs
+
+
 # ---------------------------------------------------------------------------
 # The iteration exactly as printed in the paper (comparison flag)
 # ---------------------------------------------------------------------------

@@ -47,7 +47,8 @@ class SolveArgs(C.Structure):
                 ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
                 ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
                 ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("state_warm", C.c_void_p),
-                ("state_out", C.c_void_p), ("opts", C.POINTER(Options))]
+                ("state_out", C.c_void_p), ("opts", C.POINTER(Options)),
+                ("warm_shift", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -55,7 +56,7 @@ class Request(C.Structure):
                 ("iters", C.c_int32), ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
                 ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
                 ("iters_out", C.c_void_p), ("x_warm", C.c_void_p), ("state_warm", C.c_void_p),
-                ("state_out", C.c_void_p)]
+                ("state_out", C.c_void_p), ("warm_shift", C.c_int32)]
 
 
 _lib = None

@@ -13,7 +13,7 @@ namespace prism {
 
 // Chunk sizes up to this one fit in 256 registers per lane, so two waves share
 // each SIMD and one wave's MFMA work overlaps the other's VALU work.
-constexpr int kMaxHQTwoWaves = 18;
+constexpr int kMaxHQTwoWaves = 16;
 
 template <int HQ, bool EXACT, int GEMM>
 __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
@@ -42,6 +42,8 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   T.uw = A.uw;
   T.uout = A.uout;
   T.jp = A.jp;
+  T.xsave = nullptr;
+  T.shift = A.shift;
   T.N = A.N;
   T.H = A.H;
   T.nj = A.nj;

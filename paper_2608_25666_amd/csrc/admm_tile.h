@@ -321,15 +321,16 @@ struct TileSolver {
     }
   }
 
-  // q <- (1 - alpha) C x + q for every row (first pass with alpha != 1).
-  __device__ __forceinline__ void prep_q() {
+  // q <- c C x + q for every row, with x_0 := vb in the first acceleration and
+  // jerk rows (c = 1 - alpha adds the slack of x to the relaxed state).
+  __device__ __forceinline__ void prep_q(float c, float vb) {
     float acc = 0.0f;
 #pragma unroll
     for (int i = 0; i < HQ; ++i) { acc += X(i); sw[i] = acc; }
     const float off = excl_prefix(acc);
     float xprev = lane_read(X(HQ - 1), a_prev);
     float aprev = lane_read(X(HQ - 1) - X(HQ - 2), a_prev);
-    xprev = (g == 0) ? v0 : xprev;
+    xprev = (g == 0) ? vb : xprev;
     aprev = (g == 0) ? 0.0f : aprev;
 #pragma unroll
     for (int i = 0; i < HQ; ++i) {
@@ -337,11 +338,29 @@ struct TileSolver {
       const float sj = sa - aprev;
       xprev = X(i);
       aprev = sa;
-      qv[i] = fmaf(oma, X(i), qv[i]);
-      qq[i] = fmaf(oma, sw[i] + off, qq[i]);
-      qa[i] = fmaf(oma, sa, qa[i]);
-      qj[i] = fmaf(oma, sj, qj[i]);
+      qv[i] = fmaf(c, X(i), qv[i]);
+      qq[i] = fmaf(c, sw[i] + off, qq[i]);
+      qa[i] = fmaf(c, sa, qa[i]);
+      qj[i] = fmaf(c, sj, qj[i]);
     }
+  }
+
+  // Advance a row block held as this lane's chunk (steps g*HQ .. g*HQ+HQ-1) by
+  // one step: step k takes step k+1, the last step H-1 keeps its value, rows
+  // past H stay zero. The chunk boundary comes from the next lane group.
+  __device__ __forceinline__ void shift_rows(float (&r)[HQ], int H) {
+    const float nxt_raw = lane_read(r[0], a_next);
+    const float nxt = (g == 3) ? 0.0f : nxt_raw;
+    const int lastrel = H - 1 - g * HQ;          // in [0, HQ) only for the group holding H-1
+    constexpr int kLo = HQ > 4 ? HQ - 4 : 0;     // H >= 4 HQ - 3 puts lastrel here when HQ > 2
+    float keep[HQ - kLo];
+#pragma unroll
+    for (int i = kLo; i < HQ; ++i) keep[i - kLo] = r[i];
+#pragma unroll
+    for (int i = 0; i + 1 < HQ; ++i) r[i] = r[i + 1];
+    r[HQ - 1] = nxt;
+#pragma unroll
+    for (int i = kLo; i < HQ; ++i) r[i] = (i == lastrel) ? keep[i - kLo] : r[i];
   }
 
   __device__ void run(const TileArgs& A, int j, int s0, const float* __restrict__ kf32,
@@ -395,15 +414,15 @@ struct TileSolver {
         if (i < HQ) xt_lds[i * 64 + lane] = v;
       }
     }
+    const bool shift = A.shift != 0 && A.xw != nullptr;
     if (A.xw != nullptr) {
       const float* pw = opaque(A.xw + colbase + chunk);
 #pragma unroll
       for (int i = 0; i < 4 * NB; ++i) xb[i >> 2][i & 3] = (i < HQ) ? ld_row(pw, i) : 0.0f;
     }
-    if (g == 0) xb[0][0] = v0;                 // x_1 = v0 (eq. (A_b_def))
     const size_t ubase = ((size_t)s_ld * nj + j) * 4 * H;
     if (A.uw != nullptr) {
-      // warm state: q = (1 - alpha) z + u of the previous solve (shifted by the caller)
+      // warm state: q = (1 - alpha) z + u of the previous solve
       const float* pu = opaque(A.uw + ubase + g * HQ);
 #pragma unroll
       for (int i = 0; i < HQ; ++i) {
@@ -418,9 +437,30 @@ struct TileSolver {
     } else {
 #pragma unroll
       for (int i = 0; i < HQ; ++i) { qv[i] = 0.0f; qq[i] = 0.0f; qa[i] = 0.0f; qj[i] = 0.0f; }
-      // cold start: the previous slack is C x0, so q = (1 - alpha) C x0
-      if (A.alpha != 1.0f) prep_q();
     }
+    if (shift) {
+      // Next MPC step: the multiplier and the slack's deviation from C x move one
+      // step ahead (last step repeating) and the slack is rebuilt on the shifted
+      // iterate: q' = (1 - alpha) C x' + shift(q - (1 - alpha) C x). The previous
+      // boundary value is the warm iterate's first step.
+      if (A.uw != nullptr && A.alpha != 1.0f) prep_q(-oma, lane_read(X(0), c << 2));
+      if (A.uw != nullptr) {
+        shift_rows(qv, H);
+        shift_rows(qq, H);
+        shift_rows(qa, H);
+        shift_rows(qj, H);
+        if (g == 0) { qa[0] = 0.0f; qj[0] = 0.0f; }
+      }
+      float r[HQ];
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) r[i] = X(i);
+      shift_rows(r, H);
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) xb[i >> 2][i & 3] = r[i];
+    }
+    if (g == 0) xb[0][0] = v0;                 // x_1 = v0 (eq. (A_b_def))
+    // cold start or shifted state: q += (1 - alpha) C x0 (the slack of x0)
+    if ((A.uw == nullptr || shift) && A.alpha != 1.0f) prep_q(oma, v0);
 
     const bool tolmode = A.tolmode != 0;
     const bool reduced = GEMM != GEMM_F32;
@@ -467,6 +507,16 @@ struct TileSolver {
         float* dst = po + i * st;
         if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
         *dst = v;
+      }
+    }
+    if (A.xsave != nullptr) {
+      float* po = opaque(col_ok ? A.xsave + colbase + chunk : g_store_sink);
+      const int st = col_ok ? nj : 0;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        float* dst = po + i * st;
+        if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
+        *dst = X(i);
       }
     }
     if (A.uout != nullptr) {

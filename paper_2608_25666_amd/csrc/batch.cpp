@@ -71,40 +71,10 @@ BatchKernelFn pick_batch_kernel(int set, int precision) {
 
 }  // namespace
 
-extern "C" {
+namespace prism {
 
-prism_status_t prism_batch_create(prism_batch_t* out) {
-  if (!out) return PRISM_EINVAL;
-  prism_batch_s* b = new (std::nothrow) prism_batch_s();
-  if (!b) return PRISM_ENOMEM;
-  if (hipGetDevice(&b->device) != hipSuccess) {
-    delete b;
-    return PRISM_EDEVICE;
-  }
-  if (hipMalloc((void**)&b->d_counters, 4 * sizeof(int)) != hipSuccess ||
-      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
-    prism_batch_destroy(b);
-    return PRISM_ENOMEM;
-  }
-  *out = b;
-  return PRISM_OK;
-}
-
-void prism_batch_destroy(prism_batch_t b) {
-  if (!b) return;
-  if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
-  release_tables(b);
-  if (b->d_counters) (void)hipFree(b->d_counters);
-  if (b->copied) (void)hipEventDestroy(b->copied);
-  delete b;
-}
-
-prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_request_t* reqs,
-                                      const prism_options_t* opts_in, hipStream_t stream) {
-  if (!b || n_req < 0 || (n_req > 0 && !reqs)) return PRISM_EINVAL;
-  prism_options_t opts;
-  if (opts_in) opts = *opts_in;
-  else prism_options_default(&opts);
+prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
+                             const prism_options_t& opts, hipStream_t stream) {
   prism_status_t st = validate_options(&opts);
   if (st != PRISM_OK) return st;
   int dev = -1;
@@ -114,15 +84,17 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
   size_t n_jp = 0;
   std::vector<int> live;
   for (int r = 0; r < n_req; ++r) {
-    const prism_request_t& q = reqs[r];
-    const prism_proj_s* p = q.proj;
+    const BatchDesc& q = reqs[r];
+    const prism_proj_s* p = q.p;
     if (!p || q.N < 0 || q.iters < 0 || !q.q0 || !q.v0) return PRISM_EINVAL;
+    if (q.shift != 0 && q.shift != 1) return PRISM_EINVAL;
+    if (q.shift && q.uw && !q.xw) return PRISM_EINVAL;
     if (p->device != b->device) return PRISM_EDEVICE;
     JointRowParams tmp[kMaxJoints];
     st = fill_joint_params(p, q.q0, q.v0, tmp);
     if (st != PRISM_OK) return st;
     if (q.N == 0) continue;
-    if (!q.v_samples || !q.v_out) return PRISM_EINVAL;
+    if (!q.xin || !q.xout) return PRISM_EINVAL;
     if ((long long)q.N * p->H * p->nj > (1ll << 40)) return PRISM_EINVAL;
     live.push_back(r);
     n_jp += p->nj;
@@ -131,7 +103,7 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
 
   // longest work first: chunk^2 * tiles * iterations
   auto cost = [&](int r) {
-    const prism_proj_s* p = reqs[r].proj;
+    const prism_proj_s* p = reqs[r].p;
     const double tiles = (double)((reqs[r].N + kTileCols - 1) / kTileCols) * p->nj;
     return (double)p->HQ * p->HQ * tiles * std::max(1, reqs[r].iters);
   };
@@ -140,13 +112,13 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
   // ---- which launches: one for the {5, 13, 25} set, else one per chunk class
   bool all_mpc = true;
   for (int r : live)
-    if (!batch_set_has(0, reqs[r].proj->HQ)) all_mpc = false;
+    if (!batch_set_has(0, reqs[r].p->HQ)) all_mpc = false;
   std::vector<int> sets;
   if (all_mpc) sets.push_back(0);
   else
     for (int s = 1; s <= 3; ++s)
       for (int r : live)
-        if (batch_set_has(s, reqs[r].proj->HQ)) {
+        if (batch_set_has(s, reqs[r].p->HQ)) {
           sets.push_back(s);
           break;
         }
@@ -168,21 +140,22 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
   for (int s : sets) {
     Launch L{s, (int)ri, 0, 0, 2, 0};
     for (int r : live) {
-      const prism_request_t& q = reqs[r];
-      const prism_proj_s* p = q.proj;
+      const BatchDesc& q = reqs[r];
+      const prism_proj_s* p = q.p;
       if (!batch_set_has(s, p->HQ)) continue;
       BatchReq& B = b->h_reqs[ri++];
       std::memset(&B, 0, sizeof(B));
       fill_joint_params(p, q.q0, q.v0, b->h_jp + ji);
       TileArgs& T = B.t;
-      T.xin = q.v_samples;
-      T.xout = q.v_out;
-      T.rp = q.r_primal;
-      T.rd = q.r_dual;
-      T.itout = q.iters_out;
-      T.xw = q.x_warm;
-      T.uw = q.state_warm;
-      T.uout = q.state_out;
+      T.xin = q.xin;
+      T.xout = q.xout;
+      T.xsave = q.xsave;
+      T.rp = q.rp;
+      T.rd = q.rd;
+      T.itout = q.itout;
+      T.xw = q.xw;
+      T.uw = q.uw;
+      T.uout = q.uout;
       T.jp = b->d_jp + ji;
       T.N = q.N;
       T.H = p->H;
@@ -190,6 +163,7 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
       T.iters = q.iters;
       T.check_every = opts.check_every;
       T.tolmode = tolmode ? 1 : 0;
+      T.shift = q.shift;
       T.tail = (opts.precision == PRISM_PREC_FP32) ? 0
                                                    : std::min(opts.fp32_tail, tolmode ? opts.fp32_tail : q.iters);
       T.rho = (float)(p->rho * p->w[2]);
@@ -244,6 +218,65 @@ prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_re
     if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   }
   return PRISM_OK;
+}
+
+}  // namespace prism
+
+extern "C" {
+
+prism_status_t prism_batch_create(prism_batch_t* out) {
+  if (!out) return PRISM_EINVAL;
+  prism_batch_s* b = new (std::nothrow) prism_batch_s();
+  if (!b) return PRISM_ENOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return PRISM_EDEVICE;
+  }
+  if (hipMalloc((void**)&b->d_counters, 4 * sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+    prism_batch_destroy(b);
+    return PRISM_ENOMEM;
+  }
+  *out = b;
+  return PRISM_OK;
+}
+
+void prism_batch_destroy(prism_batch_t b) {
+  if (!b) return;
+  if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
+  release_tables(b);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->copied) (void)hipEventDestroy(b->copied);
+  delete b;
+}
+
+prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_request_t* reqs,
+                                      const prism_options_t* opts_in, hipStream_t stream) {
+  if (!b || n_req < 0 || (n_req > 0 && !reqs)) return PRISM_EINVAL;
+  prism_options_t opts;
+  if (opts_in) opts = *opts_in;
+  else prism_options_default(&opts);
+  std::vector<BatchDesc> d((size_t)n_req);
+  for (int r = 0; r < n_req; ++r) {
+    const prism_request_t& q = reqs[r];
+    BatchDesc& D = d[(size_t)r];
+    D.p = q.proj;
+    D.xin = q.v_samples;
+    D.xout = q.v_out;
+    D.xsave = nullptr;
+    D.rp = q.r_primal;
+    D.rd = q.r_dual;
+    D.itout = q.iters_out;
+    D.xw = q.x_warm;
+    D.uw = q.state_warm;
+    D.uout = q.state_out;
+    D.N = q.N;
+    D.iters = q.iters;
+    D.shift = q.warm_shift;
+    D.q0 = q.q0;
+    D.v0 = q.v0;
+  }
+  return prism::enqueue_batch(b, d.data(), n_req, opts, stream);
 }
 
 }  // extern "C"

@@ -35,7 +35,9 @@ struct TileArgs {
   const float* uw;
   float* uout;
   const JointRowParams* jp;   // n_joints entries
+  float* xsave;               // second copy of x [N][H][nj] or null
   int N, H, nj, iters, check_every, tail, tolmode;
+  int shift;                  // 1: warm x and q are read one step ahead (last step repeated)
   float rho, alpha, tol, cV, cQ, cJ;
 };
 
@@ -51,6 +53,7 @@ struct SolveKernelArgs {
   const void* frag;      // FP32 fragments, then 16-bit fragments (reduced forms)
   int* counter;          // tile counter, zero at launch
   int N, H, nj, ntiles;
+  int shift;             // warm state read one step ahead
   int iters, check_every, tail, tolmode;
   float rho, alpha, tol;          // rho: penalty of the acceleration block (rho * w_A)
   float cV, cQ, cJ;               // block weights relative to the acceleration block

@@ -40,6 +40,28 @@ int solve_frag_bytes(const prism_proj_s* p, int precision);
 prism_status_t validate_options(const prism_options_t* o);
 int kernel_blocks_per_cu(const void* fn, int lds_bytes);   // occupancy, cached per (kernel, LDS)
 int device_cus();
+
+// One request of a batched launch (host-side description).
+struct BatchDesc {
+  const prism_proj_s* p;
+  const float* xin;
+  float* xout;
+  float* xsave;      // second copy of x or null
+  float* rp;
+  float* rd;
+  int* itout;
+  const float* xw;
+  const float* uw;
+  float* uout;
+  int N, iters, shift;
+  const double* q0;  // host [nj]
+  const double* v0;  // host [nj]
+};
+
+// Validates every request, then enqueues the request tables and the batched
+// launch(es) on `stream` using the staging object b (see prism_proj_solve_batch).
+prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
+                             const prism_options_t& opts, hipStream_t stream);
 hipError_t launch_feasibility(const FeasKernelArgs& a, hipStream_t stream);
 
 }  // namespace prism

@@ -318,6 +318,8 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   if (st != PRISM_OK) return st;
   if (a->N < 0 || a->iters < 0) return PRISM_EINVAL;
   if (!a->q0 || !a->v0) return PRISM_EINVAL;
+  if (a->warm_shift != 0 && a->warm_shift != 1) return PRISM_EINVAL;
+  if (a->warm_shift && a->state_warm && !a->x_warm) return PRISM_EINVAL;
   SolveKernelArgs K{};
   st = fill_joint_params(p, a->q0, a->v0, K.jp);
   if (st != PRISM_OK) return st;
@@ -342,6 +344,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.xw = a->x_warm;
   K.uw = a->state_warm;
   K.uout = a->state_out;
+  K.shift = a->warm_shift;
   K.frag = (o->precision == PRISM_PREC_FP16) ? p->frag_f16 : p->frag_bf16;
   K.N = a->N;
   K.H = p->H;

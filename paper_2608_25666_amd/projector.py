@@ -102,12 +102,13 @@ class Projector:
 
     def solve(self, samples, q0, v0, iters: int, opts: Optional[L.Options] = None,
               out=None, r_primal=None, r_dual=None, iters_out=None, x_warm=None,
-              state_warm=None, state_out=None, stream=None):
+              state_warm=None, state_out=None, warm_shift=False, stream=None):
         """Project samples ([N][H][nj] float32 on the GPU). Asynchronous on the stream.
 
         Returns (v_out, r_primal, r_dual); pass preallocated tensors to avoid
         allocation. iters_out / state_out ([N][nj][4][H] dual state q) are filled
-        when given; x_warm / state_warm warm-start the iteration.
+        when given; x_warm / state_warm warm-start the iteration, advanced by one
+        MPC step first when warm_shift is set.
         """
         import torch
         N = int(samples.shape[0])
@@ -136,6 +137,7 @@ class Projector:
         a.state_warm = None if state_warm is None else state_warm.data_ptr()
         a.state_out = None if state_out is None else state_out.data_ptr()
         a.opts = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
+        a.warm_shift = 1 if warm_shift else 0
         L.check(L.lib().prism_proj_solve_ex(self._h, C.byref(a), _stream(stream)),
                 "prism_proj_solve_ex")
         return out, r_primal, r_dual
@@ -169,7 +171,7 @@ class Batch:
 
     solve() takes a list of dicts with keys proj (a Projector), samples, q0, v0,
     iters and optionally out, r_primal, r_dual, iters_out, x_warm, state_warm,
-    state_out (tensors as for Projector.solve). Missing out / r_primal / r_dual
+    state_out (tensors as for Projector.solve) and warm_shift. Missing out / r_primal / r_dual
     are allocated. Returns the list of (v_out, r_primal, r_dual).
     """
 
@@ -222,6 +224,7 @@ class Batch:
             for f in ("iters_out", "x_warm", "state_warm", "state_out"):
                 t = r.get(f)
                 setattr(a, f, None if t is None else t.data_ptr())
+            a.warm_shift = 1 if r.get("warm_shift") else 0
             outs.append((out, rp, rd))
         po = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
         L.check(L.lib().prism_proj_solve_batch(self._h, n, arr, po, _stream(stream)),

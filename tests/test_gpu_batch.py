@@ -132,3 +132,33 @@ def test_batch_empty_and_invalid_requests():
     assert np.all(out2.cpu().numpy() == 7.0)
     B.close()
     P.close()
+
+
+def test_batch_warm_shift_equals_single():
+    """Batched requests that warm-start from a previous result advanced by one step."""
+    import torch
+    from paper_2608_25666_amd import Batch, Projector, options
+    reqs = _small_mix(8, n_requests=5)
+    o = options(alpha=1.6)
+    projs = [Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default") for r in reqs]
+    xs = [torch.from_numpy(np.ascontiguousarray(r.samples)).cuda() for r in reqs]
+    prev, states = [], []
+    for P, x, r in zip(projs, xs, reqs):
+        q = torch.zeros((r.N, r.nj, 4, r.H), dtype=torch.float32, device="cuda")
+        out, _, _ = P.solve(x, r.q0, r.v0, 30, opts=o, state_out=q)
+        prev.append(out)
+        states.append(q)
+    flipped = [torch.flip(x, dims=[0]).contiguous() for x in xs]   # next step's samples
+    B = Batch()
+    outs = B.solve([dict(proj=P, samples=f, q0=r.q0, v0=r.v0, iters=40, x_warm=p, state_warm=q,
+                         warm_shift=True)
+                    for P, f, r, p, q in zip(projs, flipped, reqs, prev, states)], opts=o)
+    singles = [P.solve(f, r.q0, r.v0, 40, opts=o, x_warm=p, state_warm=q, warm_shift=True)
+               for P, f, r, p, q in zip(projs, flipped, reqs, prev, states)]
+    torch.cuda.synchronize()
+    for (bo, brp, brd), (so, srp, srd) in zip(outs, singles):
+        np.testing.assert_array_equal(bo.cpu().numpy(), so.cpu().numpy())
+        np.testing.assert_array_equal(brp.cpu().numpy(), srp.cpu().numpy())
+    B.close()
+    for P in projs:
+        P.close()

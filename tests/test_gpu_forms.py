@@ -249,3 +249,47 @@ def test_reduced_form_residual_mode_reaches_tolerance(prec):
           f"{O.iters.mean():.0f}); max-abs vs oracle {err:.3e}, fp32 form {np.abs(xf - O.x).max():.3e}")
     assert it.mean() <= 1.3 * itf.mean() + 20
     assert err <= 5e-3
+
+
+@pytest.mark.parametrize("alpha,weights", [(1.0, None), (1.6, "default")])
+def test_warm_start_advanced_by_one_step(alpha, weights):
+    """Two MPC steps: a cold solve, then the next step's samples warm-started from its
+    result advanced by one step (warm_shift). The oracle runs the same chain from its own
+    first solve (advance_warm_start); outputs match at the FP32 bar. Computing in place
+    (x_warm = v_out, state_warm = state_out) gives the same bits."""
+    import torch
+    from paper_2608_25666_amd import Projector, options
+    from workloads import configs as WC
+    ctrl = WC.config5_controllers(seed=3, n_controllers=1)[0]
+    H, nj, N = 30, 3, 40
+    ctrl.H, ctrl.nj, ctrl.N = H, nj, N
+    ctrl.freqs, ctrl.phases = ctrl.freqs[:nj], ctrl.phases[:nj]
+    q0, v0a, v0b = ctrl.q0[:nj], ctrl.v0[:nj], 0.5 * ctrl.v0[:nj]
+    s0 = WC.controller_samples(ctrl, 0)
+    s1 = WC.controller_samples(ctrl, 1)
+    bounds = W.UR5E_BIMANUAL_BOUNDS(nj)
+    P = Projector(H, nj, ctrl.dt, bounds, 1.0, weights=weights)
+    o = options(alpha=alpha)
+    x0 = torch.from_numpy(s0).cuda()
+    x1 = torch.from_numpy(s1).cuda()
+    q = torch.zeros((N, nj, 4, H), dtype=torch.float32, device="cuda")
+    a, _, _ = P.solve(x0, q0, v0a, 50, opts=o, state_out=q)
+    qa = q.clone()
+    b, rpb, rdb = P.solve(x1, q0, v0b, 40, opts=o, x_warm=a, state_warm=qa, warm_shift=True)
+    # in place: the warm buffers are overwritten by this solve's results
+    a2, q2 = a.clone(), q.clone()
+    P.solve(x1, q0, v0b, 40, opts=o, out=a2, x_warm=a2, state_warm=q2, state_out=q2,
+            warm_shift=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a2.cpu().numpy(), b.cpu().numpy())
+    kw = dict(alpha=alpha, weights=P.weights)
+    O0 = admm.solve_request(s0, H, ctrl.dt, bounds, q0, v0a, iters=50, **kw)
+    xs, ys, zs = admm.advance_warm_start(O0.x, O0.y, O0.z, H, v0b)
+    O1 = admm.solve_request(s1, H, ctrl.dt, bounds, q0, v0b, iters=40, warm_x=xs, warm_y=ys,
+                            warm_z=zs, **kw)
+    err = np.abs(b.cpu().numpy() - O1.x).max()
+    print(f"alpha {alpha} weights {weights}: shifted warm start max-abs {err:.3e}")
+    assert err <= 1e-4
+    np.testing.assert_allclose(rpb.cpu().numpy(), O1.r_p, atol=1e-4, rtol=1e-3)
+    np.testing.assert_allclose(rdb.cpu().numpy(), O1.r_d, atol=1e-4, rtol=1e-3)
+    P.close()

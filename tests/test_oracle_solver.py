@@ -331,3 +331,42 @@ def test_warm_start_with_slack_at_solution_is_fixed_point():
                         warm_x=a.x, warm_y=a.y, warm_z=a.z, **kw)
     np.testing.assert_allclose(b.x, a.x, atol=1e-9)
     np.testing.assert_allclose(b.y, a.y, atol=1e-8)
+
+
+def test_advance_warm_start_hand_example():
+    """H = 3, one column, values worked by hand: x = (0.5, 1, 2) has C x =
+    V (0.5, 1, 2) | Q (0.5, 1.5, 3.5) | A (0.5, 0.5, 1) | J (0, 0.5); the slack
+    deviates from it by d = 0.1 * (1..11). With v0_new = -0.25 the shifted iterate
+    (-0.25, 2, 2) has C x' = V (-0.25, 2, 2) | Q (-0.25, 1.75, 3.75) |
+    A (-0.25, 2.25, 0) | J (2.5, -2.25), and the shifted deviation is
+    V (.2, .3, .3) | Q (.5, .6, .6) | A (0, .9, .9) | J (1.1, 1.1)."""
+    H = 3
+    x = np.array([0.5, 1.0, 2.0]).reshape(1, 3, 1)
+    Cx = np.array([0.5, 1, 2, 0.5, 1.5, 3.5, 0.5, 0.5, 1.0, 0.0, 0.5])
+    y = np.arange(1.0, 12.0).reshape(1, 1, 11)
+    z = (Cx + 0.1 * np.arange(1.0, 12.0)).reshape(1, 1, 11)
+    xs, ys, zs = admm.advance_warm_start(x, y, z, H, [-0.25])
+    np.testing.assert_array_equal(xs[0, :, 0], [-0.25, 2.0, 2.0])
+    np.testing.assert_array_equal(ys[0, 0], [2, 3, 3, 5, 6, 6, 0, 9, 9, 11, 11])
+    np.testing.assert_allclose(zs[0, 0], [-0.05, 2.3, 2.3, 0.25, 2.35, 4.35, -0.25, 3.15, 0.9,
+                                          3.6, -1.15], atol=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.6])
+def test_advance_warm_start_keeps_a_stationary_solution(alpha):
+    """Samples above the velocity limit and v0 at the limit: the projection is the
+    constant trajectory x = v_max with active velocity rows. Time-shifting changes
+    nothing, so the advanced state of the converged solve must pass the first residual
+    check of the next solve (iteration 0) -- which fails if any block's offset is off."""
+    H, vmax = 12, 1.4
+    lim = problem.JointLimits(-1e6, 1e6, -1.5, vmax, -7.0, 7.0, -50.0, 50.0)
+    xt = np.full((5, H), 2.0)
+    kw = dict(alpha=alpha, weights=(1.0, 0.2, 4.0, 20.0))
+    a = admm.admm_joint(xt, H, 0.05, lim, 0.1, vmax, iters=60000, tol=1e-12, check_every=50, **kw)
+    np.testing.assert_allclose(a.x, vmax, atol=1e-9)
+    xs, ys, zs = admm.advance_warm_start(a.x[:, :, None], a.y[:, None, :], a.z[:, None, :], H,
+                                         [vmax])
+    b = admm.admm_joint(xt, H, 0.05, lim, 0.1, vmax, iters=100, tol=1e-8, check_every=10,
+                        warm_x=xs[:, :, 0], warm_y=ys[:, 0], warm_z=zs[:, 0], **kw)
+    assert np.all(b.iters == 0)
+    np.testing.assert_allclose(b.x, a.x, atol=1e-9)

@@ -14,6 +14,7 @@ from .configs import (  # noqa: F401
     config3,
     config4_requests,
     config5_controllers,
+    controller_samples,
     make_request,
     sinusoid_base,
 )
