@@ -17,6 +17,10 @@ oracle timed on the host cores on a bounded sample.
                     [--alpha A] [--no-cpu-baseline] [--iters-cap C] [--workload cfg2|cfg3|cfg4]
 
 --workload cfg3: 12 joints, N = 8192, H = 100 (same generator).
+--workload cfg5: 32 controllers with config-4 sizes issue Poisson requests at 20 Hz
+each for --duration seconds into the continuous-batching server (warm start by
+shift, HBM-budget admission); `value` is the served throughput and latency is
+arrival to completion.
 --workload cfg4: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
 6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
 prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
@@ -83,7 +87,17 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--duration", type=float, default=60.0, help="cfg5: seconds of arrivals")
+    ap.add_argument("--controllers", type=int, default=32, help="cfg5: controllers")
+    ap.add_argument("--rate", type=float, default=20.0, help="cfg5: requests/s per controller")
+    ap.add_argument("--max-inflight", type=int, default=4, help="cfg5: launches in flight")
+    ap.add_argument("--max-batch", type=int, default=64, help="cfg5: requests per launch")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="cfg5: warm-state pool")
+    ap.add_argument("--grid-share", type=int, default=75, help="cfg5: percent of workgroup "
+                    "slots one launch may take")
+    ap.add_argument("--cold", action="store_true", help="cfg5: no warm start (sample "
+                    "counts alternate so no request matches its predecessor)")
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (3 times): its "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the traffic figures")
@@ -255,6 +269,126 @@ def run_batch(a):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(a):
+    """Serving: Poisson arrivals from many controllers into prism_server."""
+    import torch
+    from workloads import configs as WC
+    from paper_2608_25666_amd import Projector, Server, now_ns, options
+    from paper_2608_25666_amd import PREC_FP32, PREC_BF16, PREC_FP16
+    ctrls = WC.config5_controllers(n_controllers=a.controllers, rate_hz=a.rate,
+                                   duration_s=a.duration)
+    dev = torch.device("cuda:0")
+    n_sets = 8
+    handles = {}
+    for c in ctrls:
+        key = (c.H, c.nj, c.dt)
+        if key not in handles:
+            handles[key] = Projector(c.H, c.nj, c.dt, WC.UR5E_BIMANUAL_BOUNDS(c.nj), 1.0,
+                                     weights=None if a.weights == "unit" else "default")
+    # samples of steps 0..n_sets-1 per controller, resident before the run (request k uses
+    # step k mod n_sets)
+    sets = [[torch.from_numpy(WC.controller_samples(c, k)).to(dev) for k in range(n_sets)]
+            for c in ctrls]
+    if a.cold:       # every other request one sample short: never the predecessor's count
+        sets = [[s if k % 2 == 0 else s[:-1] for k, s in enumerate(ss)] for ss in sets]
+    arrivals = sorted((float(t), ci) for ci, c in enumerate(ctrls) for t in c.arrivals)
+    n_req = len(arrivals)
+    step_of = []
+    cnt = [0] * len(ctrls)
+    for _, ci in arrivals:
+        step_of.append(cnt[ci])
+        cnt[ci] += 1
+    sizes = [sets[ci][k % n_sets].shape[0] * ctrls[ci].nj for (_, ci), k in zip(arrivals, step_of)]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    it_all = torch.zeros(int(offs[-1]), dtype=torch.int32, device=dev)
+    rp_all = torch.zeros(int(offs[-1]), dtype=torch.float32, device=dev)
+    rd_all = torch.zeros_like(rp_all)
+    outs = [[torch.empty_like(sets[ci][0]), torch.empty_like(sets[ci][0])] for ci in range(len(ctrls))]
+
+    def one_run(prec):
+        opts = options(precision=prec, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
+                       fp32_tail=a.fp32_tail if prec == PREC_FP32 else max(a.fp32_tail, 10))
+        S = Server(budget=int(a.budget_gb * (1 << 30)), opts=opts, max_inflight=a.max_inflight,
+                   max_batch=a.max_batch, grid_share=a.grid_share)
+        ids = [S.add_controller(handles[(c.H, c.nj, c.dt)], c.N) for c in ctrls]
+        torch.cuda.synchronize()
+        tickets = []
+        t0 = now_ns() + 20_000_000
+        late = 0
+        for i, ((t, ci), k) in enumerate(zip(arrivals, step_of)):
+            due = t0 + int(t * 1e9)
+            while True:
+                d = due - now_ns()
+                if d <= 0:
+                    break
+                if d > 2_000_000:
+                    time.sleep((d - 1_000_000) / 1e9)
+            late = max(late, now_ns() - due)
+            x = sets[ci][k % n_sets]
+            o = outs[ci][k % 2][:x.shape[0]]
+            sl = slice(int(offs[i]), int(offs[i + 1]))
+            c = ctrls[ci]
+            tickets.append(S.submit(ids[ci], x, c.q0, c.v0, a.iters_cap, o,
+                                    r_primal=rp_all[sl].view(x.shape[0], c.nj),
+                                    r_dual=rd_all[sl].view(x.shape[0], c.nj),
+                                    iters_out=it_all[sl].view(x.shape[0], c.nj)))
+        infos = [S.wait(t, 120000) for t in tickets]
+        torch.cuda.synchronize()
+        stats = S.stats()
+        for t in tickets:
+            S.release(t)
+        S.close()
+        lat = np.array([(inf["t_done_ns"] - (t0 + int(t * 1e9))) / 1e6
+                        for inf, (t, _) in zip(infos, arrivals)])
+        t_end = max(inf["t_done_ns"] for inf in infos)
+        span = (t_end - t0) / 1e9
+        traj = sum(sets[ci][k % n_sets].shape[0] for (_, ci), k in zip(arrivals, step_of))
+        it_np = it_all.cpu().numpy()
+        res = np.maximum(rp_all.cpu().numpy(), rd_all.cpu().numpy())
+        col_iters = {}
+        for i, ((_, ci), k) in enumerate(zip(arrivals, step_of)):
+            H = ctrls[ci].H
+            col_iters[H] = col_iters.get(H, 0.0) + float(it_np[offs[i]:offs[i + 1]].sum())
+        warm = float(np.mean([inf["warm"] for inf in infos]))
+        return {"value": traj / span, "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                     "p99": float(np.percentile(lat, 99)),
+                                                     "max": float(lat.max())},
+                "requests": n_req, "trajectories": int(traj), "span_s": span,
+                "warm_frac": warm, "max_submit_lag_ms": late / 1e6,
+                "iterations": {"mean": float(it_np.mean()), "max": int(it_np.max()),
+                               "converged_frac": float(np.mean(res <= a.tol))},
+                "mean_batch": float(np.mean([inf["batch_size"] for inf in infos])),
+                "launches": stats["launches"], "evictions": stats["evictions"],
+                "max_concurrent_launches": stats["max_concurrent_launches"],
+                "gpu_busy_work": roofline(col_iters, span, prec == PREC_FP32)}
+
+    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
+    m = one_run(main_prec)
+    o = one_run(other)
+    line = {
+        "metric": "projected trajectories/sec at residual <=1e-3; p50/p99 request latency",
+        "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": m["requests"],
+        "warmup": 0, "ms_per_step": m["span_s"] * 1e3 / max(1, m["requests"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if main_prec == PREC_FP32 else ("bf16+f32" if main_prec == PREC_BF16
+                                                         else "f16+f32"),
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(ctrls)} controllers (config-4 sizes), Poisson "
+                               f"{a.rate:g} Hz each for {a.duration:g} s, warm start by shift, "
+                               f"HBM-budget admission, residual <= {a.tol:g}",
+                   "controllers": len(ctrls), "rate_hz": a.rate, "duration_s": a.duration,
+                   "budget_gb": a.budget_gb, "max_inflight": a.max_inflight,
+                   "max_batch": a.max_batch, "grid_share": a.grid_share, "alpha": a.alpha,
+                   "precision": a.precision,
+                   "cold": a.cold},
+        "latency_ms": m["latency_ms"], "serving": {k: v for k, v in m.items()
+                                                   if k not in ("value", "latency_ms")},
+        "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -276,6 +410,8 @@ def main():
         del src, dst
     if a.workload == "cfg4":
         return run_batch(a)
+    if a.workload == "cfg5":
+        return run_serve(a)
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     req = W.config3() if a.workload == "cfg3" else W.config2(N=a.N)
     dev = torch.device("cuda:0")

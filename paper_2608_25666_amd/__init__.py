@@ -9,3 +9,4 @@ from ._lib import (  # noqa: F401
     PREC_BF16, PREC_FP16, PREC_FP32, PrismError, load,
 )
 from .projector import Batch, Projector, default_block_weights, factor_host, options  # noqa: F401
+from .server import Server, now_ns  # noqa: F401

@@ -59,6 +59,32 @@ class Request(C.Structure):
                 ("state_out", C.c_void_p), ("warm_shift", C.c_int32)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
+                ("max_queue", C.c_int32), ("grid_share", C.c_int32), ("opts", Options)]
+
+
+class ServeRequest(C.Structure):
+    _fields_ = [("v_samples", C.c_void_p), ("N", C.c_int32), ("iters", C.c_int32),
+                ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
+                ("v_out", C.c_void_p), ("r_primal", C.c_void_p), ("r_dual", C.c_void_p),
+                ("iters_out", C.c_void_p)]
+
+
+class TicketInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("warm", C.c_int32),
+                ("batch_size", C.c_int32), ("t_submit_ns", C.c_int64), ("t_launch_ns", C.c_int64),
+                ("t_done_ns", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in
+                ("submitted", "completed", "failed", "launches", "evictions", "queued", "running",
+                 "max_concurrent_launches", "pool_bytes", "pool_used")]
+
+
+SERVER_QUEUED, SERVER_RUNNING, SERVER_DONE, SERVER_FAILED = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -107,6 +133,17 @@ def load(path: str = LIB_PATH):
         "prism_batch_destroy": (None, [H]),
         "prism_proj_solve_batch": (st, [H, C.c_int, C.POINTER(Request), C.POINTER(Options),
                                         C.c_void_p]),
+        "prism_server_config_default": (None, [C.POINTER(ServerConfig)]),
+        "prism_server_create": (st, [C.POINTER(ServerConfig), C.POINTER(H)]),
+        "prism_server_destroy": (None, [H]),
+        "prism_server_add_controller": (st, [H, H, C.c_int32, C.POINTER(C.c_int32)]),
+        "prism_server_submit": (st, [H, C.c_int32, C.POINTER(ServeRequest),
+                                     C.POINTER(C.c_int64)]),
+        "prism_server_poll": (st, [H, C.c_int64, C.POINTER(TicketInfo)]),
+        "prism_server_wait": (st, [H, C.c_int64, C.c_int64, C.POINTER(TicketInfo)]),
+        "prism_server_release": (st, [H, C.c_int64]),
+        "prism_server_stats": (st, [H, C.POINTER(ServerStats)]),
+        "prism_server_now_ns": (C.c_int64, []),
         "prism_status_str": (C.c_char_p, [C.c_int]),
         "prism_abi_version": (C.c_int, []),
     }

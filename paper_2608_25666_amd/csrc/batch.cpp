@@ -74,7 +74,7 @@ BatchKernelFn pick_batch_kernel(int set, int precision) {
 namespace prism {
 
 prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
-                             const prism_options_t& opts, hipStream_t stream) {
+                             const prism_options_t& opts, hipStream_t stream, int grid_pct) {
   prism_status_t st = validate_options(&opts);
   if (st != PRISM_OK) return st;
   int dev = -1;
@@ -211,7 +211,8 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
     A.hq_max = L.hq_max;
     const int lds = L.frag_max + kWaves * L.hq_max * 64 * (int)sizeof(float);
     const int bpc = kernel_blocks_per_cu((const void*)fn, lds);
-    const int grid = (int)std::max(1ll, std::min((long long)L.items, (long long)bpc * device_cus()));
+    const long long slots = std::max(1ll, (long long)bpc * device_cus() * grid_pct / 100);
+    const int grid = (int)std::max(1ll, std::min((long long)L.items, slots));
     void* params[] = {&A};
     if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
       return PRISM_EDEVICE;

@@ -60,8 +60,9 @@ struct BatchDesc {
 
 // Validates every request, then enqueues the request tables and the batched
 // launch(es) on `stream` using the staging object b (see prism_proj_solve_batch).
+// grid_pct caps each persistent grid at that percent of the workgroup slots.
 prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
-                             const prism_options_t& opts, hipStream_t stream);
+                             const prism_options_t& opts, hipStream_t stream, int grid_pct = 100);
 hipError_t launch_feasibility(const FeasKernelArgs& a, hipStream_t stream);
 
 }  // namespace prism

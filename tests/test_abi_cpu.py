@@ -13,7 +13,7 @@ from oracle import factor as ofactor, problem
 import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "prism_proj.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("prism_proj.h", "prism_server.h")]
 
 
 def _lib():
@@ -22,7 +22,7 @@ def _lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(prism_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))
@@ -129,3 +129,33 @@ def test_batch_null_arguments_rejected():
     assert lib.prism_batch_create(None) == L.PRISM_EINVAL
     assert lib.prism_proj_solve_batch(None, 0, None, None, None) == L.PRISM_EINVAL
     lib.prism_batch_destroy(None)
+
+
+def test_server_null_and_bad_arguments_rejected():
+    L, lib = _lib()
+    cfg = L.ServerConfig()
+    lib.prism_server_config_default(C.byref(cfg))
+    assert cfg.max_inflight == 2 and cfg.max_batch == 64 and cfg.hbm_budget == 1 << 30
+    assert cfg.grid_share == 75
+    h = C.c_void_p()
+    assert lib.prism_server_create(None, C.byref(h)) == L.PRISM_EINVAL
+    for field, bad in (("max_inflight", 0), ("max_inflight", 5), ("max_batch", 0),
+                       ("max_queue", 0), ("grid_share", 0), ("grid_share", 101),
+                       ("hbm_budget", 0)):
+        c2 = L.ServerConfig()
+        lib.prism_server_config_default(C.byref(c2))
+        setattr(c2, field, bad)
+        assert lib.prism_server_create(C.byref(c2), C.byref(h)) == L.PRISM_EINVAL, field
+    cid = C.c_int32()
+    assert lib.prism_server_add_controller(None, None, 1, C.byref(cid)) == L.PRISM_EINVAL
+    t = C.c_int64()
+    assert lib.prism_server_submit(None, 0, None, C.byref(t)) == L.PRISM_EINVAL
+    info = L.TicketInfo()
+    assert lib.prism_server_poll(None, 1, C.byref(info)) == L.PRISM_EINVAL
+    assert lib.prism_server_wait(None, 1, 0, C.byref(info)) == L.PRISM_EINVAL
+    assert lib.prism_server_release(None, 1) == L.PRISM_EINVAL
+    st = L.ServerStats()
+    assert lib.prism_server_stats(None, C.byref(st)) == L.PRISM_EINVAL
+    lib.prism_server_destroy(None)
+    a, b = lib.prism_server_now_ns(), lib.prism_server_now_ns()
+    assert 0 < a <= b

@@ -1,0 +1,192 @@
+"""The continuous-batching server (include/prism_server.h) on the GPU.
+
+* Each result is the same alone and in the mix: a controller's chain of warm-
+  started requests gives bit-identical outputs whether it is served by itself or
+  interleaved with other controllers' requests in shared launches.
+* A served chain matches the FP64 oracle's chain (advance_warm_start between
+  steps) at the FP32 bar, 1e-4 rad/s max-abs.
+* Admission under a budget smaller than all controllers' warm state evicts idle
+  state; every request still completes and cold-started ones equal a cold solve.
+* Launches overlap: a small request submitted while a large one runs finishes
+  first.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import admm
+import workloads as W
+from workloads import configs as WC
+
+pytestmark = pytest.mark.gpu
+
+
+def _controllers(seed, n, h_choices=(20, 50, 100, 33), n_choices=(16, 40, 64)):
+    cs = WC.config5_controllers(seed=seed, n_controllers=n, h_choices=h_choices,
+                                n_choices=n_choices)
+    return cs
+
+
+def _setup(ctrls, steps, weights="default"):
+    import torch
+    from paper_2608_25666_amd import Projector
+    projs = [Projector(c.H, c.nj, c.dt, W.UR5E_BIMANUAL_BOUNDS(c.nj), 1.0, weights=weights)
+             for c in ctrls]
+    samples = [[torch.from_numpy(WC.controller_samples(c, k)).cuda() for k in range(steps)]
+               for c in ctrls]
+    return projs, samples
+
+
+def _serve(server_kw, ctrls, projs, samples, order, iters):
+    """Submit requests in `order` ((controller, step) pairs); returns outputs and infos."""
+    import torch
+    from paper_2608_25666_amd import Server, options
+    S = Server(opts=options(alpha=1.6), **server_kw)
+    ids = [S.add_controller(P, c.N) for P, c in zip(projs, ctrls)]
+    outs, tickets = {}, {}
+    for ci, k in order:
+        c = ctrls[ci]
+        o = torch.empty_like(samples[ci][k])
+        rp = torch.empty((c.N, c.nj), dtype=torch.float32, device="cuda")
+        # a controller's next step is submitted once its previous step is done (MPC loop)
+        if (ci, k - 1) in tickets:
+            S.wait(tickets[(ci, k - 1)], 60000)
+        tickets[(ci, k)] = S.submit(ids[ci], samples[ci][k], c.q0, c.v0, iters, o, r_primal=rp)
+        outs[(ci, k)] = (o, rp)
+    infos = {key: S.wait(t, 60000) for key, t in tickets.items()}
+    torch.cuda.synchronize()
+    res = {key: (o.cpu().numpy(), rp.cpu().numpy()) for key, (o, rp) in outs.items()}
+    stats = S.stats()
+    for t in tickets.values():
+        S.release(t)
+    S.close()
+    return res, infos, stats
+
+
+def test_each_result_same_alone_and_in_the_mix():
+    from paper_2608_25666_amd import _lib as L
+    ctrls = _controllers(1, 6)
+    steps = 3
+    projs, samples = _setup(ctrls, steps)
+    alone = {}
+    for ci in range(len(ctrls)):
+        r, infos, _ = _serve({}, ctrls, projs, samples, [(ci, k) for k in range(steps)], 60)
+        alone.update(r)
+        assert all(i["state"] == L.SERVER_DONE for i in infos.values())
+        assert [infos[(ci, k)]["warm"] for k in range(steps)] == [False, True, True]
+    mixed_order = [(ci, k) for k in range(steps) for ci in range(len(ctrls))]
+    mix, infos, stats = _serve({"max_inflight": 3}, ctrls, projs, samples, mixed_order, 60)
+    assert stats["completed"] == len(mixed_order) and stats["failed"] == 0
+    assert max(i["batch_size"] for i in infos.values()) >= 2       # requests shared launches
+    for key in mixed_order:
+        np.testing.assert_array_equal(mix[key][0], alone[key][0], err_msg=str(key))
+        np.testing.assert_array_equal(mix[key][1], alone[key][1], err_msg=str(key))
+    print(f"launches {stats['launches']}, max concurrent {stats['max_concurrent_launches']}")
+
+
+def test_served_chain_matches_oracle_chain():
+    ctrls = _controllers(2, 1, h_choices=(20,), n_choices=(24,))
+    c = ctrls[0]
+    steps, iters = 3, 50
+    projs, samples = _setup(ctrls, steps)
+    res, infos, _ = _serve({}, ctrls, projs, samples, [(0, k) for k in range(steps)], iters)
+    bounds = W.UR5E_BIMANUAL_BOUNDS(c.nj)
+    kw = dict(alpha=1.6, weights=projs[0].weights, iters=iters)
+    prev = None
+    for k in range(steps):
+        s = samples[0][k].cpu().numpy()
+        if prev is None:
+            O = admm.solve_request(s, c.H, c.dt, bounds, c.q0, c.v0, **kw)
+        else:
+            xs, ys, zs = admm.advance_warm_start(prev.x, prev.y, prev.z, c.H, c.v0)
+            O = admm.solve_request(s, c.H, c.dt, bounds, c.q0, c.v0, warm_x=xs, warm_y=ys,
+                                   warm_z=zs, **kw)
+        err = np.abs(res[(0, k)][0] - O.x).max()
+        print(f"step {k} warm={infos[(0, k)]['warm']}: max-abs vs oracle {err:.3e}")
+        assert err <= 1e-4
+        np.testing.assert_allclose(res[(0, k)][1], O.r_p, atol=1e-4, rtol=1e-3)
+        prev = O
+
+
+def test_admission_under_a_small_budget_evicts_idle_state():
+    import torch
+    ctrls = _controllers(3, 5, h_choices=(50,), n_choices=(64,))
+    steps = 3
+    projs, samples = _setup(ctrls, steps)
+    one = 5 * 64 * 50 * max(c.nj for c in ctrls) * 4
+    budget = 2 * one + 4096                       # room for two controllers' state
+    order = [(ci, k) for k in range(steps) for ci in range(len(ctrls))]
+    res, infos, stats = _serve({"budget": budget, "max_inflight": 2}, ctrls, projs, samples,
+                               order, 40)
+    assert stats["completed"] == len(order) and stats["evictions"] > 0
+    assert stats["pool_used"] <= stats["pool_bytes"] <= budget
+    from paper_2608_25666_amd import options
+    for (ci, k), info in infos.items():
+        if info["warm"]:
+            continue
+        c = ctrls[ci]
+        cold, _, _ = projs[ci].solve(samples[ci][k], c.q0, c.v0, 40, opts=options(alpha=1.6))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(res[(ci, k)][0], cold.cpu().numpy())
+
+
+def test_launches_overlap():
+    """A small request submitted while a large one runs completes before it."""
+    import torch
+    from paper_2608_25666_amd import Projector, Server, options
+    bounds12 = W.UR5E_BIMANUAL_BOUNDS(12)
+    big_req = W.make_request(40, N=4096, H=100, nj=12, dt=0.02, kind="smooth")
+    small_req = W.make_request(41, N=16, H=20, nj=6, dt=0.05, kind="smooth")
+    Pb = Projector(100, 12, 0.02, bounds12, 1.0, weights="default")
+    Ps = Projector(20, 6, 0.05, W.UR5E_BIMANUAL_BOUNDS(6), 1.0, weights="default")
+    S = Server(opts=options(alpha=1.6), max_inflight=2)
+    cb, cs = S.add_controller(Pb, 4096), S.add_controller(Ps, 16)
+    xb = torch.from_numpy(big_req.samples).cuda()
+    xs = torch.from_numpy(small_req.samples).cuda()
+    ob, os_ = torch.empty_like(xb), torch.empty_like(xs)
+    torch.cuda.synchronize()
+    tb = S.submit(cb, xb, big_req.q0, big_req.v0, 600, ob)
+    while S.poll(tb)["state"] == 0:
+        pass
+    ts = S.submit(cs, xs, small_req.q0, small_req.v0, 50, os_)
+    ib, is_ = S.wait(tb, 60000), S.wait(ts, 60000)
+    st = S.stats()
+    print(f"big {(ib['t_done_ns'] - ib['t_launch_ns']) / 1e6:.2f} ms, small done "
+          f"{(ib['t_done_ns'] - is_['t_done_ns']) / 1e6:.2f} ms before it")
+    assert st["max_concurrent_launches"] == 2
+    assert is_["t_launch_ns"] < ib["t_done_ns"] and is_["t_done_ns"] < ib["t_done_ns"]
+    S.close()
+
+
+def test_server_errors_and_empty_requests():
+    import torch
+    from paper_2608_25666_amd import PrismError, Projector, Server, options
+    from paper_2608_25666_amd import _lib as L
+    r = W.make_request(42, N=4096, H=100, nj=12, dt=0.02, kind="smooth")
+    P = Projector(100, 12, 0.02, r.bounds, 1.0, weights="default")
+    S = Server(opts=options(alpha=1.6), max_queue=1)
+    c = S.add_controller(P, 4096)
+    x = torch.from_numpy(r.samples).cuda()
+    outs = [torch.empty_like(x) for _ in range(3)]
+    empty = torch.zeros((0, 100, 12), dtype=torch.float32, device="cuda")
+    t0 = S.submit(c, empty, r.q0, r.v0, 10, empty)
+    assert S.poll(t0)["state"] == L.SERVER_DONE
+    with pytest.raises(PrismError):
+        S.submit(c + 5, x, r.q0, r.v0, 10, outs[0])                   # unknown controller
+    with pytest.raises(PrismError):
+        S.submit(c, x, r.q0, np.full(12, 99.0), 10, outs[0])          # infeasible v0
+    t1 = S.submit(c, x, r.q0, r.v0, 2000, outs[0])
+    while S.poll(t1)["state"] == L.SERVER_QUEUED:
+        pass
+    t2 = S.submit(c, x, r.q0, r.v0, 10, outs[1])                      # waits for t1
+    with pytest.raises(PrismError) as e:
+        S.submit(c, x, r.q0, r.v0, 10, outs[2])                       # queue full
+    assert e.value.status == L.PRISM_EBUSY
+    with pytest.raises(PrismError):
+        S.release(t2)                                                 # still pending
+    assert S.wait(t2, 60000)["state"] == L.SERVER_DONE
+    S.release(t1)
+    S.release(t2)
+    with pytest.raises(PrismError):
+        S.poll(t1)
+    S.close()
