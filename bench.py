@@ -104,6 +104,34 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_sha() -> str:
+    """sha256 over the kernel sources (csrc/*.h and admm_*.hip), as recorded beside the
+    rocprofv3 counters in profiles/traffic.json."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2608_25666_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith(".h") or (f.startswith("admm_") and f.endswith(".hip")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None
+    when none were taken for this workload or the kernel sources changed since."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            t = json.load(fh).get(key)
+    except (OSError, ValueError):
+        return None
+    if not t or t.get("source_sha256") != kernel_source_sha():
+        return None
+    return 1024.0 * (t["fetch_kib_per_dispatch"] * t["fetch_factor"] +
+                     t["write_kib_per_dispatch"] * t["write_factor"])
+
+
 def _oracle_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -487,8 +515,11 @@ def main():
         roof = {"bound": "mfma", "achieved": ach, "peak": peak_mfma, "unit": "TFLOP/s",
                 "frac": ach / peak_mfma}
     roof["traffic"] = None
+    if a.workload == "cfg2" and req.N == 2048 and prec == PREC_FP32 and not fixed:
+        roof["traffic"] = measured_traffic("cfg2_fp32_tol")
+    roof["algorithmic_bytes"] = req.N * req.nj * H * 8 + req.N * req.nj * 12
     roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
-    roof["hbm_gbs"] = (req.N * req.nj * H * 8 + req.N * req.nj * 12) / kern_s / 1e9
+    roof["hbm_gbs"] = roof["algorithmic_bytes"] / kern_s / 1e9
     fixed_cols = req.N * req.nj * 100
     fixed_valu = valu_ops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
     fixed_mfma = mfma_flops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
@@ -523,6 +554,24 @@ def main():
     }
     if a.no_extras:
         line["fixed_100_iters"] = None
+    elif prec == PREC_FP32 and not fixed:
+        # the reduced-precision forms on the same batch at the same residual target
+        side = {}
+        for name, p2 in (("bf16", PREC_BF16), ("fp16", PREC_FP16)):
+            o2 = options(precision=p2, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
+                         fp32_tail=10)
+            w2, per2 = _timed(lambda: P.solve(x, req.q0, req.v0, n_it, opts=o2, out=out,
+                                              r_primal=rp, r_dual=rd, iters_out=it,
+                                              stream=stream), a.steps, a.warmup, stream)
+            res2 = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+            it2 = it.cpu().numpy()
+            side[name + "+10fp32"] = {
+                "value": req.N / (w2 / a.steps), "ms_per_step": w2 * 1e3 / a.steps,
+                "latency_ms": {"p50": float(np.percentile(per2, 50)),
+                               "p99": float(np.percentile(per2, 99))},
+                "iterations": {"max": int(it2.max()), "mean": float(it2.mean()),
+                               "converged_frac": float(np.mean(res2 <= a.tol))}}
+        line["side_by_side"] = side
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(req, a.tol, a.check_every, a.iters_cap, a.alpha,
                                             a.cpu_sample, P.weights)
