@@ -213,7 +213,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * ordered longest first and pulled by workgroups from an atomic counter.
  * A batch whose horizons all fall in {17..20, 49..52, 97..100} (chunk sizes
  * {5, 13, 25}) runs as one launch; other mixes run one launch per chunk-size
- * class (chunks 2-8, 9-16, 17-32), in order on the same stream.
+ * class (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the same stream.
  * ------------------------------------------------------------------------- */
 typedef struct prism_batch_s* prism_batch_t;   /* staging buffers for request tables */
 

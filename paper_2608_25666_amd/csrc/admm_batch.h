@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void admm_batch_kernel(BatchKernelArgs B) {
 using BatchKernelFn = void (*)(BatchKernelArgs);
 
 // Kernels by chunk-size set: 0 = {5, 13, 25} (horizons 17-20, 49-52, 97-100),
-// 1 = chunks 2..8, 2 = chunks 9..16, 3 = chunks 17..32.
+// 1 = chunks 2..8, 2 = 9..12, 3 = 13..16, 4 = 17..24, 5 = 25..32.
 BatchKernelFn batch_kernel_f32(int set);
 BatchKernelFn batch_kernel_bf16(int set);
 BatchKernelFn batch_kernel_f16(int set);
@@ -88,8 +88,10 @@ inline bool batch_set_has(int set, int hq) {
   switch (set) {
     case 0: return hq == 5 || hq == 13 || hq == 25;
     case 1: return hq >= 2 && hq <= 8;
-    case 2: return hq >= 9 && hq <= 16;
-    case 3: return hq >= 17 && hq <= 32;
+    case 2: return hq >= 9 && hq <= 12;
+    case 3: return hq >= 13 && hq <= 16;
+    case 4: return hq >= 17 && hq <= 24;
+    case 5: return hq >= 25 && hq <= 32;
     default: return false;
   }
 }

@@ -4,7 +4,8 @@
 namespace prism {
 
 BatchKernelFn batch_kernel_bf16_2(int set) {
-  if (set == 3) return admm_batch_kernel<GEMM_BF16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32>;
+  if (set == 4) return admm_batch_kernel<GEMM_BF16, 17, 18, 19, 20, 21, 22, 23, 24>;
+  if (set == 5) return admm_batch_kernel<GEMM_BF16, 25, 26, 27, 28, 29, 30, 31, 32>;
   return nullptr;
 }
 

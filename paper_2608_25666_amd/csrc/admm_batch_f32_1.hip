@@ -4,7 +4,8 @@
 namespace prism {
 
 BatchKernelFn batch_kernel_f32_1(int set) {
-  if (set == 2) return admm_batch_kernel_2w<GEMM_F32, 9, 10, 11, 12, 13, 14, 15, 16>;
+  if (set == 2) return admm_batch_kernel_2w<GEMM_F32, 9, 10, 11, 12>;
+  if (set == 3) return admm_batch_kernel<GEMM_F32, 13, 14, 15, 16>;
   return nullptr;
 }
 

@@ -129,11 +129,11 @@ struct TileSolver {
   template <bool CHECK>
   __device__ __forceinline__ float rowop(float s, float& q, float lb, float ub, float& e,
                                          float& u) const {
-    const float t = fmaf(alpha, s, q);
-    const float z = med3(t, lb, ub);
-    q = fmaf(-alpha, z, t);
-    const float w = fmaf(2.0f, z, -t) - s;
-    if constexpr (CHECK) { e = z - s; u = t - z; }
+    q = fmaf(alpha, s, q);                     // t, computed in place
+    const float z = med3(q, lb, ub);
+    const float w = fmaf(2.0f, z, -q) - s;
+    if constexpr (CHECK) { e = z - s; u = q - z; }
+    q = fmaf(-alpha, z, q);                    // q' = t - alpha z
     return w;
   }
 
@@ -473,26 +473,55 @@ struct TileSolver {
     const int f32_from = !reduced ? 0 : (tolmode ? INT_MAX : iters - A.tail);
     bool f32p = !reduced;
     int it = 0;
-    int tail_left = -1;          // FP32 iterations left in the tail after convergence
+    int tail_end = -1;           // iteration that ends the FP32 tail after convergence
+    // Check points (residuals computed): iteration 0, every check_every in residual
+    // mode, the end of the tail, and the cap. Between them the plain iterations run
+    // in branch-free inner loops, one per GEMM precision.
     for (;;) {
-      const bool chk = (it == iters) || (tolmode && (it % ce) == 0) || tail_left == 0;
-      if (chk) row_update<true>();
-      else row_update<false>();
-      if (chk && tolmode) {
+      row_update<true>();
+      if (tolmode) {
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
         if (wave_max(r) <= A.tol) {
           if (f32p || A.tail <= 0) break;
           f32p = true;
-          tail_left = A.tail;
-        } else if (tail_left == 0) {
-          tail_left = -1;
+          tail_end = it + A.tail;
+        } else if (it == tail_end) {
+          tail_end = -1;
         }
       }
       if (it == iters) break;
-      if (f32p || it >= f32_from) gemm_f32(kf32);
-      else gemm_16(k16);
-      ++it;
-      if (tail_left > 0) --tail_left;
+      int next = iters;
+      if (tolmode) {
+        const int c = (it / ce + 1) * ce;
+        next = c < next ? c : next;
+        if (tail_end > it && tail_end < next) next = tail_end;
+      }
+      if constexpr (GEMM == GEMM_F32) {
+        gemm_f32(kf32);
+        ++it;
+        while (it < next) {
+          row_update<false>();
+          gemm_f32(kf32);
+          ++it;
+        }
+      } else {
+        if (f32p || it >= f32_from) gemm_f32(kf32);
+        else gemm_16(k16);
+        ++it;
+        if (!f32p) {
+          const int e = f32_from < next ? f32_from : next;
+          while (it < e) {
+            row_update<false>();
+            gemm_16(k16);
+            ++it;
+          }
+        }
+        while (it < next) {
+          row_update<false>();
+          gemm_f32(kf32);
+          ++it;
+        }
+      }
     }
 
     // ---- store x and the per-column residuals

@@ -20,13 +20,15 @@ struct prism_batch_s {
   JointRowParams* h_jp = nullptr;    // pinned
   BatchReq* d_reqs = nullptr;
   JointRowParams* d_jp = nullptr;
-  int* d_counters = nullptr;         // one per launch of a call (up to 4)
+  int* d_counters = nullptr;         // one per launch of a call (up to kMaxLaunches)
   size_t cap_req = 0, cap_jp = 0;
   hipEvent_t copied = nullptr;
   bool pending = false;
 };
 
 namespace {
+
+constexpr int kMaxLaunches = 8;   // chunk classes per call (6 used)
 
 __global__ void zero_ints_kernel(int* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
@@ -116,7 +118,7 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
   std::vector<int> sets;
   if (all_mpc) sets.push_back(0);
   else
-    for (int s = 1; s <= 3; ++s)
+    for (int s = 1; s <= 5; ++s)
       for (int r : live)
         if (batch_set_has(s, reqs[r].p->HQ)) {
           sets.push_back(s);
@@ -196,7 +198,7 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
       hipEventRecord(b->copied, stream) != hipSuccess)
     return PRISM_EDEVICE;
   b->pending = true;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, b->d_counters, 4);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, b->d_counters, kMaxLaunches);
   if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   for (size_t li = 0; li < launches.size(); ++li) {
     const Launch& L = launches[li];
@@ -233,7 +235,7 @@ prism_status_t prism_batch_create(prism_batch_t* out) {
     delete b;
     return PRISM_EDEVICE;
   }
-  if (hipMalloc((void**)&b->d_counters, 4 * sizeof(int)) != hipSuccess ||
+  if (hipMalloc((void**)&b->d_counters, kMaxLaunches * sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
     prism_batch_destroy(b);
     return PRISM_ENOMEM;
