@@ -1,7 +1,13 @@
-// Persistent ADMM kernels: a workgroup of up to eight waves stages the permuted
+// Persistent ADMM kernels: a workgroup of four waves stages the permuted
 // inverse K in LDS once, then each wave pulls tiles (16 samples of one joint)
-// from a global counter until none are left. HBM is touched only to load the
-// samples and store the projected trajectories and residuals.
+// until none are left. HBM is touched only to load the samples and store the
+// projected trajectories and residuals.
+//
+// Tiles are queued per XCD: queue x holds the sample blocks b = x, x + 8, ...
+// (all joints of a block in a row), and workgroup w serves queue w mod 8, the
+// XCD it is dispatched to. The joints of one sample share cache lines in the
+// [N][H][joints] layout, so a block is then read and written through a single
+// L2. A wave whose queue is empty takes tiles from the next queues.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,13 +63,20 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   T.cV = A.cV;
   T.cQ = A.cQ;
   T.cJ = A.cJ;
-  for (;;) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(A.counter, 1);
-    t = __builtin_amdgcn_readfirstlane(t);
-    if (t >= A.ntiles) break;
-    const int j = t % A.nj;
-    const int sb = t / A.nj;
+  const int nblk = (A.N + kTileCols - 1) / kTileCols;
+  int x = blockIdx.x & (kXcdQueues - 1);
+  for (int probed = 0; probed < kXcdQueues;) {
+    const int in_queue = (nblk > x ? (nblk - x + kXcdQueues - 1) / kXcdQueues : 0) * A.nj;
+    int i = 0;
+    if (lane == 0) i = atomicAdd(A.counter + x, 1);
+    i = __builtin_amdgcn_readfirstlane(i);
+    if (i >= in_queue) {
+      ++probed;
+      x = (x + 1) & (kXcdQueues - 1);
+      continue;
+    }
+    const int j = i % A.nj;
+    const int sb = x + kXcdQueues * (i / A.nj);
     TileSolver<HQ, EXACT, GEMM> ts;
     ts.run(T, j, sb * kTileCols, kf32, k16, xt_wave);
   }

@@ -8,6 +8,7 @@ namespace prism {
 constexpr int kMaxJoints = 64;   // PRISM_MAX_JOINTS
 constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kTileCols = 16;    // samples per tile (MFMA N dimension)
+constexpr int kXcdQueues = 8;    // tile queues, one per XCD (MI355X has 8)
 
 enum GemmPrec : int { GEMM_F32 = 0, GEMM_BF16 = 1, GEMM_F16 = 2 };
 
@@ -51,7 +52,7 @@ struct SolveKernelArgs {
   const float* uw;       // warm dual state q [N][nj][4][H] or null
   float* uout;           // dual state q out [N][nj][4][H] or null
   const void* frag;      // FP32 fragments, then 16-bit fragments (reduced forms)
-  int* counter;          // tile counter, zero at launch
+  int* counter;          // kXcdQueues tile-queue counters, zero at launch
   int N, H, nj, ntiles;
   int shift;             // warm state read one step ahead
   int iters, check_every, tail, tolmode;

@@ -11,7 +11,7 @@
 #include "kernel_args.h"
 #include "prism_proj.h"
 
-constexpr int kCounterRing = 1024;   // tile counters per handle (in-flight early-exit solves)
+constexpr int kCounterRing = 1024;   // counter sets per handle (solves in flight), kXcdQueues each
 
 struct prism_proj_s {
   int H = 0, nj = 0, HQ = 0, device = 0;

@@ -63,7 +63,9 @@ int blocks_per_cu(const void* fn, int lds) {
   return nb;
 }
 
-__global__ void zero_counter_kernel(int* c) { *c = 0; }
+__global__ void zero_counter_kernel(int* c) {
+  if ((int)threadIdx.x < kXcdQueues) c[threadIdx.x] = 0;
+}
 
 }  // namespace
 
@@ -249,7 +251,7 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
   prism_status_t st = PRISM_OK;
   if (hipMalloc(&p->frag_bf16, tot) != hipSuccess || hipMalloc(&p->frag_f16, tot) != hipSuccess ||
       hipMalloc((void**)&p->d_bounds, sizeof(double) * 8 * n_joints) != hipSuccess ||
-      hipMalloc((void**)&p->d_counters, sizeof(int) * kCounterRing) != hipSuccess) {
+      hipMalloc((void**)&p->d_counters, sizeof(int) * kCounterRing * kXcdQueues) != hipSuccess) {
     st = PRISM_ENOMEM;
   }
   if (st == PRISM_OK) {
@@ -261,7 +263,7 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
         hipMemcpy(b + p->f32_bytes, hf.data(), p->b16_bytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_bounds, p->bnd.data(), sizeof(double) * 8 * n_joints,
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(p->d_counters, 0, sizeof(int) * kCounterRing) != hipSuccess)
+        hipMemset(p->d_counters, 0, sizeof(int) * kCounterRing * kXcdQueues) != hipSuccess)
       st = PRISM_EDEVICE;
   }
   if (st != PRISM_OK) {
@@ -363,7 +365,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.frag_f32_bytes = p->f32_bytes;
   K.frag_16_bytes = p->b16_bytes;
   const unsigned slot = p->next_counter.fetch_add(1) % kCounterRing;
-  K.counter = p->d_counters + slot;
+  K.counter = p->d_counters + (size_t)slot * kXcdQueues;
 
   const int lds = solve_lds_bytes(p, o->precision);
   const int bpc = blocks_per_cu((const void*)fn, lds);
@@ -371,7 +373,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   const long long cap = (long long)bpc * num_cus();
   const int grid = (int)std::max(1ll, std::min(want, cap));
 
-  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, K.counter);
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
   if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   void* params[] = {&K};
   if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
