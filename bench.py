@@ -21,6 +21,9 @@ oracle timed on the host cores on a bounded sample.
 each for --duration seconds into the continuous-batching server (warm start by
 shift, HBM-budget admission); `value` is the served throughput and latency is
 arrival to completion.
+--workload sigma: the single-joint diagnostic of Sec. III-C: 200,000 white-noise
+sequences (H = 15, dt = 0.1, sigma = --sigma, v0 = 0, |v| <= 1, |a| <= 2, |j| <= 4)
+projected with one joint; reports the projected spread and the FP64 feasibility.
 --workload cfg4: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
 6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
 prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
@@ -87,7 +90,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "sigma"])
+    ap.add_argument("--sigma", type=float, default=1.0, help="sigma: sampling sigma")
     ap.add_argument("--duration", type=float, default=60.0, help="cfg5: seconds of arrivals")
     ap.add_argument("--controllers", type=int, default=32, help="cfg5: controllers")
     ap.add_argument("--rate", type=float, default=20.0, help="cfg5: requests/s per controller")
@@ -417,6 +421,61 @@ def run_serve(a):
     print(json.dumps(line), flush=True)
 
 
+def run_sigma(a):
+    """sigma_eff diagnostic: project 200k single-joint white-noise sequences."""
+    import torch
+    import workloads as W
+    from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
+    H, dt = 15, 0.1
+    z, b = W.sigma_eff_workload(H=H)
+    P = Projector(H, 1, dt, b, 1.0, weights=None if a.weights == "unit" else "default")
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy((a.sigma * z).astype(np.float32)[:, :, None]).to(dev)
+    N = x.shape[0]
+    out = torch.empty_like(x)
+    rp = torch.empty((N, 1), dtype=torch.float32, device=dev)
+    rd = torch.empty_like(rp)
+    it = torch.empty((N, 1), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def measure(prec):
+        o = options(precision=prec, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
+                    fp32_tail=0 if prec == PREC_FP32 else 10)
+        wall, per = _timed(lambda: P.solve(x, [0.0], [0.0], a.iters_cap, opts=o, out=out,
+                                           r_primal=rp, r_dual=rd, iters_out=it, stream=stream),
+                           a.steps, a.warmup, stream)
+        viol = P.feasibility(out, [0.0], [0.0]).cpu().numpy()
+        i = it.cpu().numpy()
+        res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+        return {"value": N / (wall / a.steps), "ms_per_step": wall * 1e3 / a.steps,
+                "latency_ms": {"p50": float(np.percentile(per, 50)),
+                               "p99": float(np.percentile(per, 99))},
+                "sigma_eff_qp": float(out.double().std().item()),
+                "max_violation": float(viol.max()),
+                "iterations": {"max": int(i.max()), "mean": float(i.mean()),
+                               "converged_frac": float(np.mean(res <= a.tol))},
+                "roofline": roofline({H: float(i.sum())}, float(per.mean()) * 1e-3,
+                                     prec == PREC_FP32)}
+
+    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    m = measure(main_prec)
+    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
+    o = measure(other)
+    line = {"metric": "projected trajectories/sec at residual <=1e-3", "value": m["value"],
+            "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32" if main_prec == PREC_FP32 else "bf16+f32", "data": "synthetic",
+            "config": {"workload": f"sigma_eff diagnostic: 200000 single-joint N(0,{a.sigma:g}^2) "
+                                   "sequences, H=15, dt=0.1, v0=0, |v|<=1, |a|<=2, |j|<=4, "
+                                   f"residual <= {a.tol:g}", "sigma": a.sigma},
+            "latency_ms": m["latency_ms"], "sigma_eff_qp": m["sigma_eff_qp"],
+            "max_violation": m["max_violation"], "iterations": m["iterations"],
+            "roofline": m["roofline"],
+            "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -440,6 +499,8 @@ def main():
         return run_batch(a)
     if a.workload == "cfg5":
         return run_serve(a)
+    if a.workload == "sigma":
+        return run_sigma(a)
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     req = W.config3() if a.workload == "cfg3" else W.config2(N=a.N)
     dev = torch.device("cuda:0")

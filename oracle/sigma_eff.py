@@ -51,3 +51,27 @@ def sigma_eff_baseline(H: int, dt: float, n: int = 200_000, seed: int = 0,
         else:
             hi = mid
     return lo
+
+
+def qp_limits(v_max=1.0, a_max=2.0, j_max=4.0, q_free=1e6):
+    """Bounds of the QP diagnostic: velocity, acceleration and jerk only (the passage
+    lists no position bound, so position rows get a bound far outside any reach)."""
+    from .problem import JointLimits
+    return JointLimits(-q_free, q_free, -v_max, v_max, -a_max, a_max, -j_max, j_max)
+
+
+def sigma_eff_qp(z: np.ndarray, sigma: float, dt: float, v0: float = 0.0, tol: float = 1e-6,
+                 cap: int = 60000):
+    """Spread of the projected samples (Sec. III-C, QP paragraph): project sigma * z
+    (rows are samples, shape [n, H]) with the velocity, acceleration and jerk bounds and
+    x_1 = v0, then take the empirical standard deviation of all projected velocities
+    (every sample and step pooled). Returns (std, projected samples [n, H]).
+
+    The projection is the headline ADMM run to max(r_p, r_d) <= tol, block weights
+    (1, 2.5/H, 4, 20), alpha 1.6.
+    """
+    from . import admm
+    H = z.shape[1]
+    r = admm.admm_joint(sigma * z, H, dt, qp_limits(), 0.0, v0, alpha=1.6, iters=cap, tol=tol,
+                        check_every=50, weights=(1.0, 2.5 / H, 4.0, 20.0))
+    return float(r.x.std()), r.x

@@ -145,3 +145,36 @@ def test_sigma_eff_baseline_matches_paper(H):
     # a step of 0.05 s would give a four times smaller value: the pin fixes the dt^2 scaling
     s2 = sigma_eff_baseline(H, 0.05, n=50_000)
     assert s2 < 0.5 * g["baseline_sigma_eff"]
+
+
+def test_sigma_eff_qp_feasible_regime_is_the_identity():
+    """Below the baseline's sigma_eff every white-noise sample already meets the bounds,
+    so the projection only pins x_1 = v0 and the spread is that of the draws with the
+    first step set to v0 (exactly, on the same draws)."""
+    from oracle.sigma_eff import sigma_eff_qp
+    rng = np.random.Generator(np.random.PCG64(5))
+    z = rng.standard_normal((400, 15))
+    sigma = 1e-3
+    s, x = sigma_eff_qp(z, sigma, 0.1, v0=0.0, tol=1e-12)
+    ref = sigma * z.copy()
+    ref[:, 0] = 0.0
+    np.testing.assert_allclose(x, ref, atol=1e-13)
+    assert abs(s - ref.std()) <= 1e-12
+
+
+def test_sigma_eff_qp_is_bounded_and_grows_with_sigma():
+    """Projected velocities lie within |v| <= 1 (so the spread is below 1) and their
+    spread grows with the sampling sigma (common draws)."""
+    from oracle.sigma_eff import sigma_eff_qp
+    rng = np.random.Generator(np.random.PCG64(6))
+    z = rng.standard_normal((300, 15))
+    prev = 0.0
+    for sigma in (0.05, 0.3, 1.0, 3.0):
+        s, x = sigma_eff_qp(z, sigma, 0.1, tol=1e-7)
+        assert np.abs(x).max() <= 1.0 + 1e-6
+        a = np.diff(x, axis=1) / 0.1
+        j = np.diff(x, n=2, axis=1) / 0.01
+        assert np.abs(a).max() <= 2.0 + 1e-5 and np.abs(j).max() <= 4.0 + 1e-4
+        assert s > prev
+        prev = s
+    assert prev < 1.0

@@ -15,6 +15,7 @@ from .configs import (  # noqa: F401
     config4_requests,
     config5_controllers,
     controller_samples,
+    sigma_eff_workload,
     make_request,
     sinusoid_base,
 )

@@ -201,3 +201,14 @@ def controller_samples(ctrl: Controller, step: int, noise: float = 0.5,
     n = ctrl.N if N is None else N
     s = base[None, :, :] + rng.normal(0.0, noise, size=(n, ctrl.H, ctrl.nj))
     return np.ascontiguousarray(s, dtype=np.float32)
+
+
+def sigma_eff_workload(n: int = 200_000, H: int = 15, seed: int = 0):
+    """Single-joint diagnostic of Sec. III-C: n standard-normal velocity sequences of
+    length H (scaled by the sampling sigma by the caller), bounds |v| <= 1, |a| <= 2,
+    |j| <= 4 and no position bound (a limit of 1e6 rad stands in for none).
+    Returns (z [n][H] float64, Bounds for one joint)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((n, H))
+    b = Bounds.symmetric(1, 1e6, 1.0, 2.0, 4.0)
+    return z, b
