@@ -38,6 +38,7 @@
 #ifndef PRISM_PROJ_H
 #define PRISM_PROJ_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -246,6 +247,63 @@ void prism_batch_destroy(prism_batch_t b);
  * exactly what prism_proj_solve_ex would produce for it alone. */
 prism_status_t prism_proj_solve_batch(prism_batch_t b, int n_req, const prism_request_t* reqs,
                                       const prism_options_t* opts, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * One iteration of the sampling optimizer around the projection (Alg. 1 with a
+ * synthetic cost in place of the simulator rollouts):
+ *   1. draw x~_n = nu + sigma .* z_n, z standard normal (the Gaussian of Alg. 1;
+ *      diagonal covariance sigma^2), in the solve kernel's load: element e of
+ *      [N][H][n_joints] (row-major index) takes Philox4x32-10 at counter
+ *      (e mod 2^32, e div 2^32, stream mod 2^32, stream div 2^32), key
+ *      (seed mod 2^32, seed div 2^32); with its first two words as 23-bit
+ *      uniforms u = (w div 2^9 + 1/2) / 2^23, z = sqrt(-2 ln u0) cos(2 pi u1);
+ *   2. project every sample (Sec. III; the handle's factor and options);
+ *   3. score each projected sample: c_n = sum_k sum_j w_pos (theta_kj - ref_kj)^2
+ *      + w_vel x_kj^2 with theta_k = q0 + dt sum_{i<=k} x_i (eq. (pos_stack)),
+ *      summed in FP64 over joints;
+ *   4. weights omega_n = exp(-c_n / tau) / sum_m exp(-c_m / tau)
+ *      (eq. (weight_update)), computed in FP64 with the minimum cost taken out;
+ *   5. nu' = sum_n omega_n x_n (eq. (mean_update_new)) and
+ *      var' = sum_n omega_n (x_n - nu')^2 + eps (diagonal of eq. (cov_update_new)),
+ *      accumulated in FP64, stored FP32; best = argmin_n c_n (lowest index on ties).
+ * All device arrays are row-major FP32 unless stated; caller-owned.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* nu;          /* device [H][n_joints]: mean of the sampling Gaussian      */
+  const float* sigma;       /* device [H][n_joints]: standard deviations                */
+  uint64_t seed;            /* generator key                                            */
+  uint64_t stream;          /* generator stream (e.g. the optimizer iteration)          */
+  int32_t N;                /* samples, >= 1                                            */
+  int32_t iters;            /* iteration count / cap of the projection                  */
+  const double* q0;         /* host [n_joints]                                          */
+  const double* v0;         /* host [n_joints]                                          */
+  const float* theta_ref;   /* device [H][n_joints]: reference positions (rad)          */
+  float w_pos, w_vel;       /* cost weights, >= 0                                       */
+  float tau;                /* softmax temperature, > 0                                 */
+  float eps;                /* covariance floor, >= 0                                   */
+  float* x_out;             /* device [N][H][n_joints]: projected samples               */
+  float* samples_out;       /* device [N][H][n_joints] or NULL: the drawn samples       */
+  double* cost;             /* device [N] or NULL: c_n                                  */
+  double* omega;            /* device [N] or NULL: weights                              */
+  float* nu_out;            /* device [H][n_joints]: nu'                                */
+  float* var_out;           /* device [H][n_joints]: var'                               */
+  int32_t* best;            /* device [1] or NULL: index of the lowest-cost sample      */
+  float* r_primal;          /* device [N][n_joints] or NULL                             */
+  float* r_dual;            /* device [N][n_joints] or NULL                             */
+  int32_t* iters_out;       /* device [N][n_joints] or NULL                             */
+  void* workspace;          /* device, prism_plan_workspace_bytes(H, n_joints, N) bytes */
+  size_t workspace_bytes;
+  const prism_options_t* opts;   /* NULL = the handle's options                        */
+} prism_plan_args_t;
+
+/* Device workspace one prism_plan_step call needs (0 for invalid sizes). */
+size_t prism_plan_workspace_bytes(int H, int n_joints, int N);
+
+/* Enqueues the iteration on `stream`. PRISM_EINVAL (bad pointer, N < 1, tau <= 0,
+ * negative weights or eps, small workspace), PRISM_EINFEASIBLE (as
+ * prism_proj_solve); nothing is enqueued on error. Calls that share a workspace
+ * must be ordered (same stream). */
+prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream);
 
 /* prism_proj_feasibility -- FP64 final check of trajectories (device kernel).
  * For each column writes to viol (device, float64 [N][n_joints][5]) the largest

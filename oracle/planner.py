@@ -10,7 +10,8 @@ a value is defined on 32-bit integers (the random-number generator).
 Random numbers (the paper draws from the Gaussian; it names no generator): the
 counter-based Philox4x32-10 generator (Salmon, Moraes, Dror and Shaw, "Parallel
 random numbers: as easy as 1, 2, 3", SC'11), one call per sample element, turned
-into a standard normal by the Box-Muller transform of its first two words.
+into a standard normal by the Box-Muller transform of its first two words
+(23-bit uniforms).
 The synthetic cost (the paper's costs come from MuJoCo rollouts, Sec. IV-C): a
 joint-space tracking term w_pos * (theta_k - theta_ref_k)^2 on the positions
 integrated from the projected velocities (eq. (pos_stack)) plus w_vel * v_k^2,
@@ -58,16 +59,16 @@ def standard_normals(shape, seed: int, stream: int) -> np.ndarray:
 
     Element e takes Philox4x32-10 at counter (e mod 2^32, e div 2^32, stream mod
     2^32, stream div 2^32) with key (seed mod 2^32, seed div 2^32); its first two
-    words w0, w1 give uniforms u = (floor(w / 2^8) + 1/2) / 2^24 in (0, 1), and
-    z = sqrt(-2 ln u0) cos(2 pi u1).
+    words w0, w1 give uniforms u = (floor(w / 2^9) + 1/2) / 2^23 in (0, 1) (23 bits,
+    so u is exact in single precision as well), and z = sqrt(-2 ln u0) cos(2 pi u1).
     """
     n = int(np.prod(shape))
     e = np.arange(n, dtype=np.uint64)
     ctr = [e & MASK, e >> np.uint64(32), np.uint64(stream & MASK), np.uint64(stream >> 32)]
     key = [np.uint64(seed & MASK), np.uint64(seed >> 32)]
     w = philox4x32_10(ctr, key)
-    u0 = ((w[0] >> np.uint32(8)).astype(np.float64) + 0.5) / 16777216.0
-    u1 = ((w[1] >> np.uint32(8)).astype(np.float64) + 0.5) / 16777216.0
+    u0 = ((w[0] >> np.uint32(9)).astype(np.float64) + 0.5) / 8388608.0
+    u1 = ((w[1] >> np.uint32(9)).astype(np.float64) + 0.5) / 8388608.0
     z = np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
     return z.reshape(shape)
 

@@ -59,6 +59,19 @@ class Request(C.Structure):
                 ("state_out", C.c_void_p), ("warm_shift", C.c_int32)]
 
 
+class PlanArgs(C.Structure):
+    _fields_ = [("nu", C.c_void_p), ("sigma", C.c_void_p), ("seed", C.c_uint64),
+                ("stream", C.c_uint64), ("N", C.c_int32), ("iters", C.c_int32),
+                ("q0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
+                ("theta_ref", C.c_void_p), ("w_pos", C.c_float), ("w_vel", C.c_float),
+                ("tau", C.c_float), ("eps", C.c_float), ("x_out", C.c_void_p),
+                ("samples_out", C.c_void_p), ("cost", C.c_void_p), ("omega", C.c_void_p),
+                ("nu_out", C.c_void_p), ("var_out", C.c_void_p), ("best", C.c_void_p),
+                ("r_primal", C.c_void_p), ("r_dual", C.c_void_p), ("iters_out", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("opts", C.POINTER(Options))]
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
                 ("max_queue", C.c_int32), ("grid_share", C.c_int32), ("opts", Options)]
@@ -133,6 +146,8 @@ def load(path: str = LIB_PATH):
         "prism_batch_destroy": (None, [H]),
         "prism_proj_solve_batch": (st, [H, C.c_int, C.POINTER(Request), C.POINTER(Options),
                                         C.c_void_p]),
+        "prism_plan_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
+        "prism_plan_step": (st, [H, C.POINTER(PlanArgs), C.c_void_p]),
         "prism_server_config_default": (None, [C.POINTER(ServerConfig)]),
         "prism_server_create": (st, [C.POINTER(ServerConfig), C.POINTER(H)]),
         "prism_server_destroy": (None, [H]),

@@ -21,7 +21,7 @@ namespace prism {
 // each SIMD and one wave's MFMA work overlaps the other's VALU work.
 constexpr int kMaxHQTwoWaves = 16;
 
-template <int HQ, bool EXACT, int GEMM>
+template <int HQ, bool EXACT, int GEMM, bool PLAN = false>
 __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   {
@@ -50,6 +50,10 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
   T.jp = A.jp;
   T.xsave = nullptr;
   T.shift = A.shift;
+  T.gen_on = A.gen_on;
+  T.cost_on = A.cost_on;
+  T.gen = A.gen;
+  T.cost = A.cost;
   T.N = A.N;
   T.H = A.H;
   T.nj = A.nj;
@@ -77,7 +81,7 @@ __device__ __forceinline__ void solve_body(const SolveKernelArgs& A) {
     }
     const int j = i % A.nj;
     const int sb = x + kXcdQueues * (i / A.nj);
-    TileSolver<HQ, EXACT, GEMM> ts;
+    TileSolver<HQ, EXACT, GEMM, PLAN> ts;
     ts.run(T, j, sb * kTileCols, kf32, k16, xt_wave);
   }
 }
@@ -100,6 +104,17 @@ SolveKernelFn kernel_for() {
   if constexpr (HQ <= kMaxHQTwoWaves) return admm_solve_kernel_2w<HQ, EXACT, GEMM>;
   else return admm_solve_kernel<HQ, EXACT, GEMM>;
 }
+
+// Optimizer-step variant: samples drawn in the load, tracking cost in the
+// epilogue (one wave per SIMD; used by prism_plan_step).
+template <int HQ, int GEMM>
+__global__ __launch_bounds__(256) void admm_plan_kernel(SolveKernelArgs A) {
+  solve_body<HQ, false, GEMM, true>(A);
+}
+
+SolveKernelFn plan_kernel_f32(int HQ);
+SolveKernelFn plan_kernel_bf16(int HQ);
+SolveKernelFn plan_kernel_f16(int HQ);
 
 // Kernel for chunk size HQ (2..32), exact fit (4*HQ == H) and GEMM precision.
 SolveKernelFn solve_kernel_f32(int HQ, bool exact);

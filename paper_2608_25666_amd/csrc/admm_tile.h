@@ -47,6 +47,30 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
+// Standard normal for sample element e: Philox4x32-10 (Salmon et al., SC'11) at
+// counter (e, stream) with key (seed); Box-Muller of its first two words as
+// 23-bit uniforms (exact in FP32).
+__device__ __forceinline__ float philox_normal(unsigned long long e, const SampleGen& G) {
+  unsigned c0 = (unsigned)e, c1 = (unsigned)(e >> 32), c2 = G.stream_lo, c3 = G.stream_hi;
+  unsigned k0 = G.seed_lo, k1 = G.seed_hi;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const unsigned lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  const float u0 = ((float)(c0 >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  const float u1 = ((float)(c1 >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  return sqrtf(-2.0f * logf(u0)) * cospif(2.0f * u1);
+}
+
 __device__ __forceinline__ float lane_read(float v, int src_byte_addr) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte_addr, __float_as_int(v)));
 }
@@ -76,7 +100,7 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-template <int HQ, bool EXACT, int GEMM>
+template <int HQ, bool EXACT, int GEMM, bool PLAN = false>
 struct TileSolver {
   static constexpr int NB = (HQ + 3) / 4;    // 16-row output blocks (4 registers each)
   static constexpr int NJ4 = (HQ + 3) / 4;   // FP32 k-steps, grouped by four
@@ -405,7 +429,30 @@ struct TileSolver {
       const float v = p[r * nj];
       return (i < nvalid) ? v : 0.0f;
     };
-    {
+    if (PLAN && A.gen_on) {
+      // draw the samples: x~ = nu + sigma * z, one generator call per element
+      const SampleGen& G = A.gen;
+#pragma unroll 1
+      for (int i = 0; i < HQ; ++i) {
+        const bool ok = EXACT || i < nvalid;
+        const int k = ok ? g * HQ + i : 0;
+        const float z = philox_normal(((unsigned long long)s_ld * H + k) * nj + j, G);
+        const int pj = k * nj + j;
+        xt_lds[i * 64 + lane] = ok ? fmaf(G.sigma[pj], z, G.nu[pj]) : 0.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < 4 * NB; ++i) xb[i >> 2][i & 3] = (i < HQ) ? xt_lds[i * 64 + lane] : 0.0f;
+      if (G.xs_out != nullptr) {
+        float* po = opaque(col_ok ? G.xs_out + colbase + chunk : g_store_sink);
+        const int st = col_ok ? nj : 0;
+#pragma unroll
+        for (int i = 0; i < HQ; ++i) {
+          float* dst = po + i * st;
+          if (!(EXACT || i < HQ - 3)) dst = (i < nvalid) ? dst : g_store_sink;
+          *dst = X(i);
+        }
+      }
+    } else {
       const float* px = opaque(A.xin + colbase + chunk);
 #pragma unroll
       for (int i = 0; i < 4 * NB; ++i) {
@@ -522,6 +569,32 @@ struct TileSolver {
           ++it;
         }
       }
+    }
+
+    if (PLAN && A.cost_on) {
+      // tracking cost of this column: w_pos (theta_k - ref_k)^2 + w_vel x_k^2 with
+      // theta_k = q0 + dt * (sum of x up to step k); rows past H hold x = 0
+      const CostArgs& Cg = A.cost;
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        acc += X(i);
+        sw[i] = acc;
+      }
+      const float off = excl_prefix(acc);
+      const float q0j = A.jp[j].q0;
+      float c = 0.0f;
+#pragma unroll
+      for (int i = 0; i < HQ; ++i) {
+        const bool ok = EXACT || i < nvalid;
+        const int k = ok ? g * HQ + i : 0;
+        const float d = fmaf(Cg.dt, sw[i] + off, q0j - Cg.ref[k * nj + j]);
+        const float t = fmaf(Cg.w_pos * d, d, Cg.w_vel * X(i) * X(i));
+        c += ok ? t : 0.0f;
+      }
+      c += __shfl_xor(c, 16, 64);
+      c += __shfl_xor(c, 32, 64);
+      if (g == 0 && col_ok) Cg.cost[(size_t)s * nj + j] = c;
     }
 
     // ---- store x and the per-column residuals

@@ -22,7 +22,24 @@ struct JointRowParams {
   float lb[4];
   float ub[4];
   float v0;
-  float pad[3];
+  float q0;          // start position (used by the tracking cost)
+  float pad[2];
+};
+
+// Samples drawn in the load instead of read: x~ = nu + sigma * z, z standard
+// normal from Philox4x32-10 (counter: element index, stream; key: seed).
+struct SampleGen {
+  const float* nu;      // [H][nj]
+  const float* sigma;   // [H][nj]
+  float* xs_out;        // drawn samples [N][H][nj] or null
+  unsigned seed_lo, seed_hi, stream_lo, stream_hi;
+};
+
+// Tracking cost of each projected column, written per (sample, joint).
+struct CostArgs {
+  const float* ref;     // theta_ref [H][nj]
+  float* cost;          // [N][nj]
+  float w_pos, w_vel, dt;
 };
 
 // What one tile needs to know about its request (single solve or batch entry).
@@ -40,6 +57,9 @@ struct TileArgs {
   int N, H, nj, iters, check_every, tail, tolmode;
   int shift;                  // 1: warm x and q are read one step ahead (last step repeated)
   float rho, alpha, tol, cV, cQ, cJ;
+  int gen_on, cost_on;        // sample in the load / cost in the epilogue
+  SampleGen gen;
+  CostArgs cost;
 };
 
 struct SolveKernelArgs {
@@ -55,6 +75,9 @@ struct SolveKernelArgs {
   int* counter;          // kXcdQueues tile-queue counters, zero at launch
   int N, H, nj, ntiles;
   int shift;             // warm state read one step ahead
+  int gen_on, cost_on;
+  SampleGen gen;
+  CostArgs cost;
   int iters, check_every, tail, tolmode;
   float rho, alpha, tol;          // rho: penalty of the acceleration block (rho * w_A)
   float cV, cQ, cJ;               // block weights relative to the acceleration block

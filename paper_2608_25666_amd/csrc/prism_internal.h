@@ -38,7 +38,12 @@ SolveKernelFn pick_kernel(int HQ, bool exact, int precision);
 int solve_lds_bytes(const prism_proj_s* p, int precision);
 int solve_frag_bytes(const prism_proj_s* p, int precision);
 prism_status_t validate_options(const prism_options_t* o);
-int kernel_blocks_per_cu(const void* fn, int lds_bytes);   // occupancy, cached per (kernel, LDS)
+int kernel_blocks_per_cu(const void* fn, int lds_bytes);
+// Fills the solver fields of K (the caller sets samples, outputs, N, iters, jp and
+// the optional sampling / cost parts), clears the tile queues and launches fn.
+prism_status_t launch_solve(const prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                            SolveKernelFn fn, hipStream_t stream);
+prism_status_t check_device(const prism_proj_s* p);   // occupancy, cached per (kernel, LDS)
 int device_cus();
 
 // One request of a batched launch (host-side description).

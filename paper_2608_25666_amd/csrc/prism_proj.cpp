@@ -20,15 +20,19 @@
 
 using namespace prism;
 
-namespace {
-
-bool is_fin(double v) { return std::isfinite(v); }
+namespace prism {
 
 prism_status_t check_device(const prism_proj_s* p) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return PRISM_EDEVICE;
   return dev == p->device ? PRISM_OK : PRISM_EDEVICE;
 }
+
+}  // namespace prism
+
+namespace {
+
+bool is_fin(double v) { return std::isfinite(v); }
 
 struct LaunchInfo {
   int blocks_per_cu = 0;
@@ -118,7 +122,8 @@ prism_status_t fill_joint_params(const prism_proj_s* p, const double* q0, const 
     r.lb[3] = (float)(jmin * dt * dt);
     r.ub[3] = (float)(jmax * dt * dt);
     r.v0 = (float)v0[j];
-    r.pad[0] = r.pad[1] = r.pad[2] = 0.0f;
+    r.q0 = (float)q0[j];
+    r.pad[0] = r.pad[1] = 0.0f;
   }
   return PRISM_OK;
 }
@@ -138,6 +143,44 @@ int solve_frag_bytes(const prism_proj_s* p, int precision) {
 
 int solve_lds_bytes(const prism_proj_s* p, int precision) {
   return solve_frag_bytes(p, precision) + kWaves * p->HQ * 64 * (int)sizeof(float);
+}
+
+prism_status_t launch_solve(const prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                            SolveKernelFn fn, hipStream_t stream) {
+  const int tiles_per_joint = (K.N + kTileCols - 1) / kTileCols;
+  const long long ntiles = (long long)tiles_per_joint * p->nj;
+  if (ntiles > 0x7fffffff) return PRISM_EINVAL;
+  K.frag = (o->precision == PRISM_PREC_FP16) ? p->frag_f16 : p->frag_bf16;
+  K.H = p->H;
+  K.nj = p->nj;
+  K.ntiles = (int)ntiles;
+  K.check_every = o->check_every;
+  K.tolmode = (o->tol > 0.0f) ? 1 : 0;
+  K.tail = (o->precision == PRISM_PREC_FP32) ? 0 : std::min(o->fp32_tail, K.tolmode ? o->fp32_tail : K.iters);
+  K.rho = (float)(p->rho * p->w[2]);
+  K.cV = (float)(p->w[0] / p->w[2]);
+  K.cQ = (float)(p->w[1] / p->w[2]);
+  K.cJ = (float)(p->w[3] / p->w[2]);
+  K.alpha = o->alpha;
+  K.tol = o->tol;
+  K.frag_f32_bytes = p->f32_bytes;
+  K.frag_16_bytes = p->b16_bytes;
+  const unsigned slot = const_cast<prism_proj_s*>(p)->next_counter.fetch_add(1) % kCounterRing;
+  K.counter = p->d_counters + (size_t)slot * kXcdQueues;
+
+  const int lds = solve_lds_bytes(p, o->precision);
+  const int bpc = blocks_per_cu((const void*)fn, lds);
+  const long long want = (ntiles + kWaves - 1) / kWaves;
+  const long long cap = (long long)bpc * num_cus();
+  const int grid = (int)std::max(1ll, std::min(want, cap));
+
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
+  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  void* params[] = {&K};
+  if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
+    return PRISM_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  return PRISM_OK;
 }
 
 }  // namespace prism
@@ -334,10 +377,6 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   const bool exact = (4 * p->HQ == p->H);
   SolveKernelFn fn = pick_kernel(p->HQ, exact, o->precision);
   if (!fn) return PRISM_EUNSUPPORTED;
-  const int tiles_per_joint = (a->N + kTileCols - 1) / kTileCols;
-  const long long ntiles = (long long)tiles_per_joint * p->nj;
-  if (ntiles > 0x7fffffff) return PRISM_EINVAL;
-
   K.xin = a->v_samples;
   K.xout = a->v_out;
   K.rp = a->r_primal;
@@ -347,39 +386,9 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.uw = a->state_warm;
   K.uout = a->state_out;
   K.shift = a->warm_shift;
-  K.frag = (o->precision == PRISM_PREC_FP16) ? p->frag_f16 : p->frag_bf16;
   K.N = a->N;
-  K.H = p->H;
-  K.nj = p->nj;
-  K.ntiles = (int)ntiles;
   K.iters = a->iters;
-  K.check_every = o->check_every;
-  K.tolmode = (o->tol > 0.0f) ? 1 : 0;
-  K.tail = (o->precision == PRISM_PREC_FP32) ? 0 : std::min(o->fp32_tail, K.tolmode ? o->fp32_tail : a->iters);
-  K.rho = (float)(p->rho * p->w[2]);
-  K.cV = (float)(p->w[0] / p->w[2]);
-  K.cQ = (float)(p->w[1] / p->w[2]);
-  K.cJ = (float)(p->w[3] / p->w[2]);
-  K.alpha = o->alpha;
-  K.tol = o->tol;
-  K.frag_f32_bytes = p->f32_bytes;
-  K.frag_16_bytes = p->b16_bytes;
-  const unsigned slot = p->next_counter.fetch_add(1) % kCounterRing;
-  K.counter = p->d_counters + (size_t)slot * kXcdQueues;
-
-  const int lds = solve_lds_bytes(p, o->precision);
-  const int bpc = blocks_per_cu((const void*)fn, lds);
-  const long long want = (ntiles + kWaves - 1) / kWaves;
-  const long long cap = (long long)bpc * num_cus();
-  const int grid = (int)std::max(1ll, std::min(want, cap));
-
-  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
-  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
-  void* params[] = {&K};
-  if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
-    return PRISM_EDEVICE;
-  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
-  return PRISM_OK;
+  return launch_solve(p, K, o, fn, stream);
 }
 
 prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N, const double* q0,

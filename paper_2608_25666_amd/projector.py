@@ -142,6 +142,48 @@ class Projector:
                 "prism_proj_solve_ex")
         return out, r_primal, r_dual
 
+    def plan_step(self, nu, sigma, N: int, seed: int, stream_id: int, q0, v0, theta_ref,
+                  w_pos: float, w_vel: float, tau: float, eps: float, iters: int,
+                  opts: Optional[L.Options] = None, samples_out=None, r_primal=None,
+                  r_dual=None, iters_out=None, workspace=None, stream=None):
+        """One optimizer iteration (prism_plan_step): draw N samples from
+        N(nu, diag(sigma^2)) on the device, project, score, weight, update moments.
+        nu, sigma, theta_ref: [H][nj] float32 on the GPU. Returns a dict of tensors
+        x, cost, omega, nu, var, best (and samples when samples_out is given)."""
+        import torch
+        dev = nu.device
+        x = torch.empty((N, self.H, self.nj), dtype=torch.float32, device=dev)
+        cost = torch.empty(N, dtype=torch.float64, device=dev)
+        omega = torch.empty(N, dtype=torch.float64, device=dev)
+        nu_out = torch.empty((self.H, self.nj), dtype=torch.float32, device=dev)
+        var_out = torch.empty_like(nu_out)
+        best = torch.empty(1, dtype=torch.int32, device=dev)
+        nbytes = int(L.lib().prism_plan_workspace_bytes(self.H, self.nj, int(N)))
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
+        v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
+        a = L.PlanArgs()
+        a.nu, a.sigma, a.theta_ref = nu.data_ptr(), sigma.data_ptr(), theta_ref.data_ptr()
+        a.seed, a.stream, a.N, a.iters = int(seed), int(stream_id), int(N), int(iters)
+        a.q0 = C.cast(q0a, C.POINTER(C.c_double))
+        a.v0 = C.cast(v0a, C.POINTER(C.c_double))
+        a.w_pos, a.w_vel, a.tau, a.eps = float(w_pos), float(w_vel), float(tau), float(eps)
+        a.x_out, a.cost, a.omega = x.data_ptr(), cost.data_ptr(), omega.data_ptr()
+        a.nu_out, a.var_out, a.best = nu_out.data_ptr(), var_out.data_ptr(), best.data_ptr()
+        a.samples_out = None if samples_out is None else samples_out.data_ptr()
+        a.r_primal = None if r_primal is None else r_primal.data_ptr()
+        a.r_dual = None if r_dual is None else r_dual.data_ptr()
+        a.iters_out = None if iters_out is None else iters_out.data_ptr()
+        a.workspace, a.workspace_bytes = workspace.data_ptr(), int(workspace.numel())
+        a.opts = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
+        L.check(L.lib().prism_plan_step(self._h, C.byref(a), _stream(stream)), "prism_plan_step")
+        out = {"x": x, "cost": cost, "omega": omega, "nu": nu_out, "var": var_out, "best": best,
+               "workspace": workspace}
+        if samples_out is not None:
+            out["samples"] = samples_out
+        return out
+
     def feasibility(self, v, q0, v0, out=None, stream=None):
         """FP64 per-column violations [N][nj][5]: position, velocity, acceleration, jerk, |x1-v0|."""
         import torch

@@ -159,3 +159,15 @@ def test_server_null_and_bad_arguments_rejected():
     lib.prism_server_destroy(None)
     a, b = lib.prism_server_now_ns(), lib.prism_server_now_ns()
     assert 0 < a <= b
+
+
+def test_plan_workspace_and_null_arguments():
+    L, lib = _lib()
+    assert lib.prism_plan_workspace_bytes(1, 2, 10) == 0
+    assert lib.prism_plan_workspace_bytes(20, 0, 10) == 0
+    assert lib.prism_plan_workspace_bytes(20, 2, 0) == 0
+    n = lib.prism_plan_workspace_bytes(50, 12, 2048)
+    # per-column costs, costs and weights, best index, moment partials (8 blocks)
+    assert n >= 2048 * 12 * 4 + 2 * 2048 * 8 + 4 + 8 * 600 * 16 and n % 256 == 0
+    a = L.PlanArgs()
+    assert lib.prism_plan_step(None, C.byref(a), None) == L.PRISM_EINVAL

@@ -1,0 +1,119 @@
+"""One optimizer iteration on the GPU (prism_plan_step) against the oracle's
+(oracle/planner.py): the drawn samples, the projected samples, the costs, the
+softmax weights, the updated mean and variance, and the lowest-cost index.
+
+Tolerances: the drawn samples differ from the FP64 oracle only by the FP32
+evaluation of ln and cos in Box-Muller (stated 1e-5 absolute for |z| <= 6);
+projected samples at a fixed count 1e-4 (the FP32 bar); costs 1e-4 relative;
+weights 1e-3 relative (a cost error dc changes a weight by dc / tau); mean and
+variance 1e-4 absolute. The lowest-cost index is compared where the oracle's best
+cost is unique by more than the cost tolerance; otherwise the GPU's pick must have
+a cost within that tolerance of the minimum.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import planner
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(N=48, H=20, nj=3, dt=0.05, seed=3):
+    import torch
+    from paper_2608_25666_amd import Projector
+    r = W.make_request(seed, N=1, H=H, nj=nj, dt=dt, kind="white")
+    P = Projector(H, nj, dt, r.bounds, 1.0, weights="default")
+    rng = np.random.default_rng(seed)
+    nu = 0.3 * rng.normal(size=(H, nj))
+    sigma = np.full((H, nj), 1.2)
+    ref = r.q0[None, :] + np.cumsum(np.full((H, nj), 0.02), axis=0)
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    return P, r, nu, sigma, ref, t(nu), t(sigma), t(ref)
+
+
+def test_plan_step_matches_oracle():
+    import torch
+    from paper_2608_25666_amd import options
+    P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup()
+    N, H, nj = 48, 20, 3
+    kw = dict(w_pos=5.0, w_vel=0.2, tau=2.0, eps=1e-3)
+    drawn = torch.empty((N, H, nj), dtype=torch.float32, device="cuda")
+    o = options(alpha=1.6)
+    g = P.plan_step(nu_t, sigma_t, N, seed=11, stream_id=4, q0=r.q0, v0=r.v0, theta_ref=ref_t,
+                    iters=120, opts=o, samples_out=drawn, **kw)
+    torch.cuda.synchronize()
+    # the oracle draws from the FP32-rounded nu and sigma the kernel reads
+    nu32, sg32 = nu.astype(np.float32).astype(np.float64), sigma.astype(np.float32).astype(np.float64)
+    O = planner.plan_step(nu32, sg32, N, 11, 4, H, r.dt, r.bounds, r.q0, r.v0,
+                          ref.astype(np.float32).astype(np.float64), iters=120, alpha=1.6,
+                          weights=P.weights, **kw)
+    err_s = np.abs(drawn.cpu().numpy() - O.samples).max()
+    err_x = np.abs(g["x"].cpu().numpy() - O.x).max()
+    c = g["cost"].cpu().numpy()
+    w = g["omega"].cpu().numpy()
+    print(f"drawn {err_s:.2e}, projected {err_x:.2e}, cost rel "
+          f"{np.abs(c / O.cost - 1).max():.2e}, weight rel {np.abs(w / O.omega - 1).max():.2e}")
+    assert err_s <= 1e-5
+    assert err_x <= 1e-4
+    np.testing.assert_allclose(c, O.cost, rtol=1e-4)
+    np.testing.assert_allclose(w, O.omega, rtol=1e-3, atol=1e-12)
+    assert abs(w.sum() - 1.0) < 1e-12
+    np.testing.assert_allclose(g["nu"].cpu().numpy(), O.nu, atol=1e-4)
+    np.testing.assert_allclose(g["var"].cpu().numpy(), O.var, atol=1e-4)
+    b = int(g["best"].cpu().numpy()[0])
+    srt = np.sort(O.cost)
+    if srt[1] - srt[0] > 1e-4 * abs(srt[0]):
+        assert b == O.best
+    else:
+        assert O.cost[b] - srt[0] <= 1e-4 * abs(srt[0])
+    P.close()
+
+
+def test_plan_step_reproducible_and_streams_differ():
+    import torch
+    P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup(N=32)
+    kw = dict(w_pos=1.0, w_vel=0.1, tau=1.0, eps=1e-4, iters=30)
+    a = P.plan_step(nu_t, sigma_t, 32, 5, 0, r.q0, r.v0, ref_t, **kw)
+    b = P.plan_step(nu_t, sigma_t, 32, 5, 0, r.q0, r.v0, ref_t, **kw)
+    c = P.plan_step(nu_t, sigma_t, 32, 5, 1, r.q0, r.v0, ref_t, **kw)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+    np.testing.assert_array_equal(a["nu"].cpu().numpy(), b["nu"].cpu().numpy())
+    assert np.abs(a["x"].cpu().numpy() - c["x"].cpu().numpy()).max() > 0.1
+    P.close()
+
+
+def test_updated_mean_is_feasible():
+    """nu' is a convex combination of projected samples, hence (up to the residual)
+    inside the feasible set: checked with the FP64 feasibility kernel."""
+    import torch
+    from paper_2608_25666_amd import options
+    P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup(N=256, seed=4)
+    g = P.plan_step(nu_t, sigma_t, 256, 9, 2, r.q0, r.v0, ref_t, w_pos=2.0, w_vel=0.1, tau=5.0,
+                    eps=1e-3, iters=20000, opts=options(alpha=1.6, tol=1e-5))
+    viol = P.feasibility(g["nu"][None].contiguous(), r.q0, r.v0)
+    torch.cuda.synchronize()
+    v = viol.cpu().numpy()
+    print(f"updated mean violation per block {v.max(axis=(0, 1))}")
+    # residual 1e-5 in velocity units: 1e-5 rad/s, 2e-4 rad/s^2, 4e-3 rad/s^3 at dt 0.05
+    assert v[..., 1].max() <= 1e-5 and v[..., 2].max() <= 2e-4 and v[..., 3].max() <= 4e-3
+    P.close()
+
+
+def test_plan_step_rejects_bad_arguments():
+    import torch
+    from paper_2608_25666_amd import PrismError
+    P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup(N=16)
+    for bad in (dict(tau=0.0), dict(tau=-1.0), dict(eps=-1.0), dict(w_pos=-1.0)):
+        kw = dict(w_pos=1.0, w_vel=0.1, tau=1.0, eps=1e-4)
+        kw.update(bad)
+        with pytest.raises(PrismError):
+            P.plan_step(nu_t, sigma_t, 16, 1, 0, r.q0, r.v0, ref_t, iters=10, **kw)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    from paper_2608_25666_amd import _lib as L
+    n = L.lib().prism_plan_workspace_bytes(P.H, P.nj, 16)
+    assert n > 16
+    P.close()
