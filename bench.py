@@ -24,6 +24,9 @@ arrival to completion.
 --workload sigma: the single-joint diagnostic of Sec. III-C: 200,000 white-noise
 sequences (H = 15, dt = 0.1, sigma = --sigma, v0 = 0, |v| <= 1, |a| <= 2, |j| <= 4)
 projected with one joint; reports the projected spread and the FP64 feasibility.
+--workload plan: one optimizer iteration (prism_plan_step) per step on the config-2
+shape: draw 2048 samples from N(nu, diag sigma^2) on the device, project them to
+residual <= 1e-3, score them (tracking cost), softmax weights, mean/variance update.
 --workload cfg4: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
 6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
 prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
@@ -90,7 +93,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "sigma"])
+    ap.add_argument("--workload", default="cfg2",
+                    choices=["cfg2", "cfg3", "cfg4", "cfg5", "sigma", "plan"])
     ap.add_argument("--sigma", type=float, default=1.0, help="sigma: sampling sigma")
     ap.add_argument("--duration", type=float, default=60.0, help="cfg5: seconds of arrivals")
     ap.add_argument("--controllers", type=int, default=32, help="cfg5: controllers")
@@ -330,12 +334,15 @@ def run_serve(a):
     for _, ci in arrivals:
         step_of.append(cnt[ci])
         cnt[ci] += 1
-    sizes = [sets[ci][k % n_sets].shape[0] * ctrls[ci].nj for (_, ci), k in zip(arrivals, step_of)]
+    sizes = [sets[ci][(k + 1) % n_sets].shape[0] * ctrls[ci].nj
+             for (_, ci), k in zip(arrivals, step_of)]
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     it_all = torch.zeros(int(offs[-1]), dtype=torch.int32, device=dev)
     rp_all = torch.zeros(int(offs[-1]), dtype=torch.float32, device=dev)
     rd_all = torch.zeros_like(rp_all)
     outs = [[torch.empty_like(sets[ci][0]), torch.empty_like(sets[ci][0])] for ci in range(len(ctrls))]
+
+    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
 
     def one_run(prec):
         opts = options(precision=prec, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
@@ -343,11 +350,27 @@ def run_serve(a):
         S = Server(budget=int(a.budget_gb * (1 << 30)), opts=opts, max_inflight=a.max_inflight,
                    max_batch=a.max_batch, grid_share=a.grid_share)
         ids = [S.add_controller(handles[(c.H, c.nj, c.dt)], c.N) for c in ctrls]
+        # warm-up (untimed): every controller's step 0, so kernels are loaded and each
+        # controller holds a warm state when the arrival clock starts
+        warm = [S.submit(ids[ci], sets[ci][0], c.q0, c.v0, a.iters_cap, outs[ci][1])
+                for ci, c in enumerate(ctrls)]
+        for t in warm:
+            S.wait(t, 120000)
+            S.release(t)
         torch.cuda.synchronize()
         tickets = []
+        lags = np.zeros(len(arrivals))
+        import gc
+        gc.collect()
+        gc.disable()          # a collection pass over the live tickets stalls the submitter
         t0 = now_ns() + 20_000_000
         late = 0
+        next_report = 5.0
         for i, ((t, ci), k) in enumerate(zip(arrivals, step_of)):
+            if t >= next_report:
+                print(f"[serve {a.precision if prec == main_prec else 'other'}] {t:.0f} s of "
+                      f"arrivals, {i} requests submitted", file=sys.stderr, flush=True)
+                next_report += 5.0
             due = t0 + int(t * 1e9)
             while True:
                 d = due - now_ns()
@@ -355,8 +378,9 @@ def run_serve(a):
                     break
                 if d > 2_000_000:
                     time.sleep((d - 1_000_000) / 1e9)
+            lags[i] = (now_ns() - due) / 1e6
             late = max(late, now_ns() - due)
-            x = sets[ci][k % n_sets]
+            x = sets[ci][(k + 1) % n_sets]
             o = outs[ci][k % 2][:x.shape[0]]
             sl = slice(int(offs[i]), int(offs[i + 1]))
             c = ctrls[ci]
@@ -365,6 +389,7 @@ def run_serve(a):
                                     r_dual=rd_all[sl].view(x.shape[0], c.nj),
                                     iters_out=it_all[sl].view(x.shape[0], c.nj)))
         infos = [S.wait(t, 120000) for t in tickets]
+        gc.enable()
         torch.cuda.synchronize()
         stats = S.stats()
         for t in tickets:
@@ -374,7 +399,7 @@ def run_serve(a):
                         for inf, (t, _) in zip(infos, arrivals)])
         t_end = max(inf["t_done_ns"] for inf in infos)
         span = (t_end - t0) / 1e9
-        traj = sum(sets[ci][k % n_sets].shape[0] for (_, ci), k in zip(arrivals, step_of))
+        traj = sum(sets[ci][(k + 1) % n_sets].shape[0] for (_, ci), k in zip(arrivals, step_of))
         it_np = it_all.cpu().numpy()
         res = np.maximum(rp_all.cpu().numpy(), rd_all.cpu().numpy())
         col_iters = {}
@@ -387,6 +412,8 @@ def run_serve(a):
                                                      "max": float(lat.max())},
                 "requests": n_req, "trajectories": int(traj), "span_s": span,
                 "warm_frac": warm, "max_submit_lag_ms": late / 1e6,
+                "submit_lag_ms": {"p50": float(np.percentile(lags, 50)),
+                                  "p99": float(np.percentile(lags, 99))},
                 "iterations": {"mean": float(it_np.mean()), "max": int(it_np.max()),
                                "converged_frac": float(np.mean(res <= a.tol))},
                 "mean_batch": float(np.mean([inf["batch_size"] for inf in infos])),
@@ -476,6 +503,64 @@ def run_sigma(a):
     print(json.dumps(line), flush=True)
 
 
+def run_plan(a):
+    """Optimizer iterations around the projection on the config-2 shape."""
+    import torch
+    import workloads as W
+    from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
+    req = W.config2(N=a.N)
+    H, nj, N = req.H, req.nj, req.N
+    P = Projector(H, nj, req.dt, req.bounds, req.rho,
+                  weights=None if a.weights == "unit" else "default")
+    dev = torch.device("cuda:0")
+    rng = np.random.Generator(np.random.PCG64(1))
+    base = req.samples.mean(axis=0)                         # the batch's smooth base
+    nu = torch.from_numpy(base.astype(np.float32)).to(dev)
+    sigma = torch.full((H, nj), 0.5, dtype=torch.float32, device=dev)
+    ref = torch.from_numpy((req.q0[None, :] + req.dt * np.cumsum(base, axis=0)
+                            + 0.05 * rng.standard_normal((H, nj))).astype(np.float32)).to(dev)
+    it = torch.empty((N, nj), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    ws = None
+    step_id = [0]
+
+    def measure(prec):
+        nonlocal ws
+        o = options(precision=prec, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
+                    fp32_tail=0 if prec == PREC_FP32 else 10)
+
+        def one():
+            nonlocal ws
+            step_id[0] += 1
+            g = P.plan_step(nu, sigma, N, 7, step_id[0], req.q0, req.v0, ref, w_pos=10.0,
+                            w_vel=0.1, tau=1.0, eps=1e-3, iters=a.iters_cap, opts=o,
+                            iters_out=it, workspace=ws, stream=stream)
+            ws = g["workspace"]
+        wall, per = _timed(one, a.steps, a.warmup, stream)
+        i = it.cpu().numpy()
+        return {"value": N / (wall / a.steps), "ms_per_step": wall * 1e3 / a.steps,
+                "latency_ms": {"p50": float(np.percentile(per, 50)),
+                               "p99": float(np.percentile(per, 99))},
+                "iterations": {"max": int(i.max()), "mean": float(i.mean())}}
+
+    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
+    m = measure(main_prec)
+    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
+    o2 = measure(other)
+    line = {"metric": "projected trajectories/sec at residual <=1e-3", "value": m["value"],
+            "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32" if main_prec == PREC_FP32 else "bf16+f32", "data": "synthetic",
+            "config": {"workload": f"optimizer iteration: {N} samples drawn on the device from "
+                                   f"N(nu, 0.5^2), {nj} joints, H={H}, dt={req.dt}, projection "
+                                   f"to residual <= {a.tol:g}, tracking cost, softmax "
+                                   "weights (tau 1), mean/variance update"},
+            "latency_ms": m["latency_ms"], "iterations": m["iterations"],
+            "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o2}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -501,6 +586,8 @@ def main():
         return run_serve(a)
     if a.workload == "sigma":
         return run_sigma(a)
+    if a.workload == "plan":
+        return run_plan(a)
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     req = W.config3() if a.workload == "cfg3" else W.config2(N=a.N)
     dev = torch.device("cuda:0")

@@ -98,7 +98,10 @@ void finish_slot(prism_server_s* S, Slot& sl, prism_status_t st) {
   S->cv_done.notify_all();
 }
 
-void launch(prism_server_s* S, Slot& sl, const std::vector<serve::Pick>& picks) {
+// Called with the lock held; releases it around the HIP calls (only the worker
+// touches the slots, and running tickets cannot be released or erased).
+void launch(prism_server_s* S, Slot& sl, const std::vector<serve::Pick>& picks,
+            std::unique_lock<std::mutex>& lk) {
   std::vector<BatchDesc> d;
   d.reserve(picks.size());
   const int64_t t = mono_ns();
@@ -131,9 +134,12 @@ void launch(prism_server_s* S, Slot& sl, const std::vector<serve::Pick>& picks) 
     sl.jobs.push_back(pk.ticket);
     ++S->running;
   }
-  prism_status_t st =
-      enqueue_batch(sl.staging, d.data(), (int)d.size(), S->cfg.opts, sl.stream, S->cfg.grid_share);
+  const prism_options_t opts = S->cfg.opts;
+  const int share = S->cfg.grid_share;
+  lk.unlock();
+  prism_status_t st = enqueue_batch(sl.staging, d.data(), (int)d.size(), opts, sl.stream, share);
   if (st == PRISM_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = PRISM_EDEVICE;
+  lk.lock();
   if (st != PRISM_OK) {
     finish_slot(S, sl, st);
     return;
@@ -167,7 +173,7 @@ void worker_main(prism_server_s* S) {
         if (S->sched.queued() == 0) break;
         const std::vector<serve::Pick> picks = S->sched.pick();
         if (picks.empty()) break;
-        launch(S, sl, picks);
+        launch(S, sl, picks, lk);
         did = true;
         any_busy = any_busy || sl.busy;
       }
