@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="cfg5: warm-state pool")
     ap.add_argument("--grid-share", type=int, default=75, help="cfg5: percent of workgroup "
                     "slots one launch may take")
+    ap.add_argument("--no-side", action="store_true", help="cfg4/cfg5/sigma/plan: skip the "
+                    "second precision")
     ap.add_argument("--cold", action="store_true", help="cfg5: no warm start (sample "
                     "counts alternate so no request matches its predecessor)")
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
@@ -424,7 +426,7 @@ def run_serve(a):
     main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
     m = one_run(main_prec)
-    o = one_run(other)
+    o = None if a.no_side else one_run(other)
     line = {
         "metric": "projected trajectories/sec at residual <=1e-3; p50/p99 request latency",
         "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": m["requests"],
