@@ -132,21 +132,25 @@ struct TileSolver {
     return i < nvalid ? v : 0.0f;
   }
 
+  // Sums over the lower / higher chunks of the column. The three partner reads are
+  // independent (one LDS round trip); the sum is formed as T_near + (T_mid + T_far).
   __device__ __forceinline__ float excl_prefix(float T) const {   // sum over lower chunks
-    float a = lane_read(T, a_prev);
+    float a = lane_read(T, a_prev);    // chunk g-1
+    float b = lane_read(T, a_prev2);   // chunk g-2
+    float c = lane_read(T, a_next);    // chunk g-3 (lane - 48 = lane + 16 mod 64)
     a = (g == 0) ? 0.0f : a;
-    const float p2 = T + a;
-    float b = lane_read(p2, a_prev2);
     b = (g < 2) ? 0.0f : b;
-    return a + b;
+    c = (g < 3) ? 0.0f : c;
+    return a + (b + c);
   }
   __device__ __forceinline__ float excl_suffix(float T) const {   // sum over higher chunks
-    float a = lane_read(T, a_next);
+    float a = lane_read(T, a_next);    // chunk g+1
+    float b = lane_read(T, a_next2);   // chunk g+2
+    float c = lane_read(T, a_prev);    // chunk g+3 (lane + 48 = lane - 16 mod 64)
     a = (g == 3) ? 0.0f : a;
-    const float p2 = T + a;
-    float b = lane_read(p2, a_next2);
     b = (g >= 2) ? 0.0f : b;
-    return a + b;
+    c = (g >= 1) ? 0.0f : c;
+    return a + (b + c);
   }
 
   // One constraint row: slack clip and multiplier update from s = (C x)_row.
