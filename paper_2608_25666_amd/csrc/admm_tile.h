@@ -331,21 +331,23 @@ struct TileSolver {
         const int j = 8 * jj + e;
         dv[jj][e] = (j < HQ) ? (ST)sw[j] : (ST)0.0f;
       }
-    v4u a = k16[0];
+    // K fragments stream from LDS up to kDepth ahead of their MFMA, so the LDS
+    // latency is paid about once per GEMM instead of once per MFMA
+    constexpr int NT = NB * NJ8;
+    constexpr int kDepth = NT < 8 ? NT : (HQ >= 15 ? 4 : 8);
+    v4u ring[kDepth];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    for (int t = 0; t < kDepth; ++t) ring[t] = k16[t * 64];
 #pragma unroll
-      for (int jj = 0; jj < NJ8; ++jj) {
-        const int idx = b * NJ8 + jj;
-        v4u an = a;
-        if (idx + 1 < NB * NJ8) an = k16[(idx + 1) * 64];
-        if constexpr (GEMM == GEMM_BF16)
-          xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), dv[jj], xb[b], 0, 0, 0);
-        else
-          xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), dv[jj], xb[b], 0, 0, 0);
-        a = an;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    for (int idx = 0; idx < NT; ++idx) {
+      const int b = idx / NJ8, jj = idx % NJ8;
+      const v4u a = ring[idx % kDepth];
+      if (idx + kDepth < NT) ring[idx % kDepth] = k16[(idx + kDepth) * 64];
+      if constexpr (GEMM == GEMM_BF16)
+        xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), dv[jj], xb[b], 0, 0, 0);
+      else
+        xb[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), dv[jj], xb[b], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 
