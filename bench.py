@@ -14,20 +14,20 @@ solve kernel (timed live with HIP events on the solve's stream) and the FP64
 oracle timed on the host cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16|fp16]
-                    [--alpha A] [--no-cpu-baseline] [--iters-cap C] [--workload cfg2|cfg3|cfg4]
+                    [--alpha A] [--no-cpu-baseline] [--iters-cap C] [--workload mpc|long|uneven|serve|sigma|plan]
 
---workload cfg3: 12 joints, N = 8192, H = 100 (same generator).
---workload cfg5: 32 controllers with config-4 sizes issue Poisson requests at 20 Hz
+--workload long: 12 joints, N = 8192, H = 100 (same generator).
+--workload serve: 32 controllers with the uneven requests' sizes issue Poisson requests at 20 Hz
 each for --duration seconds into the continuous-batching server (warm start by
 shift, HBM-budget admission); `value` is the served throughput and latency is
 arrival to completion.
 --workload sigma: the single-joint diagnostic of Sec. III-C: 200,000 white-noise
 sequences (H = 15, dt = 0.1, sigma = --sigma, v0 = 0, |v| <= 1, |a| <= 2, |j| <= 4)
 projected with one joint; reports the projected spread and the FP64 feasibility.
---workload plan: one optimizer iteration (prism_plan_step) per step on the config-2
-shape: draw 2048 samples from N(nu, diag sigma^2) on the device, project them to
+--workload plan: one optimizer iteration (prism_plan_step) per step on the default
+batch shape: draw 2048 samples from N(nu, diag sigma^2) on the device, project them to
 residual <= 1e-3, score them (tracking cost), softmax weights, mean/variance update.
---workload cfg4: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
+--workload uneven: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
 6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
 prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
 --precision one).
@@ -58,7 +58,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def valu_ops_per_col_iter(H: int) -> float:
-    """Algorithmic FP32 VALU operations of one column-iteration (see DESIGN.md).
+    """Algorithmic FP32 VALU operations of one column-iteration.
 
     Forward rows C x: position prefix sums (H), acceleration (H) and jerk (H)
     differences. Row update on 4H-1 rows: t, z = clip(t), q, w (5 each).
@@ -93,20 +93,20 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
-    ap.add_argument("--workload", default="cfg2",
-                    choices=["cfg2", "cfg3", "cfg4", "cfg5", "sigma", "plan"])
+    ap.add_argument("--workload", default="mpc",
+                    choices=["mpc", "long", "uneven", "serve", "sigma", "plan"])
     ap.add_argument("--sigma", type=float, default=1.0, help="sigma: sampling sigma")
-    ap.add_argument("--duration", type=float, default=60.0, help="cfg5: seconds of arrivals")
-    ap.add_argument("--controllers", type=int, default=32, help="cfg5: controllers")
-    ap.add_argument("--rate", type=float, default=20.0, help="cfg5: requests/s per controller")
-    ap.add_argument("--max-inflight", type=int, default=4, help="cfg5: launches in flight")
-    ap.add_argument("--max-batch", type=int, default=64, help="cfg5: requests per launch")
-    ap.add_argument("--budget-gb", type=float, default=4.0, help="cfg5: warm-state pool")
-    ap.add_argument("--grid-share", type=int, default=75, help="cfg5: percent of workgroup "
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--controllers", type=int, default=32, help="serve: controllers")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: requests/s per controller")
+    ap.add_argument("--max-inflight", type=int, default=4, help="serve: launches in flight")
+    ap.add_argument("--max-batch", type=int, default=64, help="serve: requests per launch")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: warm-state pool")
+    ap.add_argument("--grid-share", type=int, default=75, help="serve: percent of workgroup "
                     "slots one launch may take")
-    ap.add_argument("--no-side", action="store_true", help="cfg4/cfg5/sigma/plan: skip the "
+    ap.add_argument("--no-side", action="store_true", help="uneven/serve/sigma/plan: skip the "
                     "second precision")
-    ap.add_argument("--cold", action="store_true", help="cfg5: no warm start (sample "
+    ap.add_argument("--cold", action="store_true", help="serve: no warm start (sample "
                     "counts alternate so no request matches its predecessor)")
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (3 times): its "
@@ -231,7 +231,7 @@ def run_batch(a):
     import torch
     import workloads as W
     from paper_2608_25666_amd import Batch, Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
-    reqs = W.config4_requests()
+    reqs = W.uneven_requests()
     dev = torch.device("cuda:0")
     handles = {}
     for r in reqs:
@@ -310,10 +310,10 @@ def run_batch(a):
 def run_serve(a):
     """Serving: Poisson arrivals from many controllers into prism_server."""
     import torch
-    from workloads import configs as WC
+    from workloads import recipes as WC
     from paper_2608_25666_amd import Projector, Server, now_ns, options
     from paper_2608_25666_amd import PREC_FP32, PREC_BF16, PREC_FP16
-    ctrls = WC.config5_controllers(n_controllers=a.controllers, rate_hz=a.rate,
+    ctrls = WC.serving_controllers(n_controllers=a.controllers, rate_hz=a.rate,
                                    duration_s=a.duration)
     dev = torch.device("cuda:0")
     n_sets = 8
@@ -435,7 +435,7 @@ def run_serve(a):
         "dtype": "f32" if main_prec == PREC_FP32 else ("bf16+f32" if main_prec == PREC_BF16
                                                          else "f16+f32"),
         "data": "synthetic",
-        "config": {"workload": f"serving: {len(ctrls)} controllers (config-4 sizes), Poisson "
+        "config": {"workload": f"serving: {len(ctrls)} controllers (uneven-request sizes), Poisson "
                                f"{a.rate:g} Hz each for {a.duration:g} s, warm start by shift, "
                                f"HBM-budget admission, residual <= {a.tol:g}",
                    "controllers": len(ctrls), "rate_hz": a.rate, "duration_s": a.duration,
@@ -506,11 +506,11 @@ def run_sigma(a):
 
 
 def run_plan(a):
-    """Optimizer iterations around the projection on the config-2 shape."""
+    """Optimizer iterations around the projection on the default batch shape."""
     import torch
     import workloads as W
     from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
-    req = W.config2(N=a.N)
+    req = W.mpc_batch(N=a.N)
     H, nj, N = req.H, req.nj, req.N
     P = Projector(H, nj, req.dt, req.bounds, req.rho,
                   weights=None if a.weights == "unit" else "default")
@@ -566,8 +566,9 @@ def run_plan(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: every column is an "
-                          "independent QP, see DESIGN.md for how the batch would shard; "
+        print(json.dumps({"error": "this benchmark measures one GPU: every (sample, joint) "
+                          "column is an independent QP with no exchange step, so a batch "
+                          "shards by samples or requests across GPUs without communication; "
                           "run with --gpus 1"}))
         sys.exit(2)
     import torch
@@ -582,16 +583,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.workload == "cfg4":
+    if a.workload == "uneven":
         return run_batch(a)
-    if a.workload == "cfg5":
+    if a.workload == "serve":
         return run_serve(a)
     if a.workload == "sigma":
         return run_sigma(a)
     if a.workload == "plan":
         return run_plan(a)
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
-    req = W.config3() if a.workload == "cfg3" else W.config2(N=a.N)
+    req = W.long_horizon_batch() if a.workload == "long" else W.mpc_batch(N=a.N)
     dev = torch.device("cuda:0")
     P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho,
                   weights=None if a.weights == "unit" else "default")
@@ -629,7 +630,7 @@ def main():
     res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
     converged = float(np.mean(res <= a.tol))
 
-    # fixed-count throughput (the configuration's 100 iterations)
+    # fixed-count throughput (100 iterations)
     fixed_ms = float("nan")
     if not a.no_extras:
         fopts = options(precision=prec, alpha=a.alpha, fp32_tail=a.fp32_tail)
@@ -665,8 +666,8 @@ def main():
         roof = {"bound": "mfma", "achieved": ach, "peak": peak_mfma, "unit": "TFLOP/s",
                 "frac": ach / peak_mfma}
     roof["traffic"] = None
-    if a.workload == "cfg2" and req.N == 2048 and prec == PREC_FP32 and not fixed:
-        roof["traffic"] = measured_traffic("cfg2_fp32_tol")
+    if a.workload == "mpc" and req.N == 2048 and prec == PREC_FP32 and not fixed:
+        roof["traffic"] = measured_traffic("mpc_N2048_H50_J12_fp32_residual")
     roof["algorithmic_bytes"] = req.N * req.nj * H * 8 + req.N * req.nj * 12
     roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
     roof["hbm_gbs"] = roof["algorithmic_bytes"] / kern_s / 1e9

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _small_mix(seed, h_choices=(20, 50, 100), n_choices=(16, 37, 64), n_requests=10):
-    return W.config4_requests(seed=seed, n_requests=n_requests, n_choices=n_choices,
+    return W.uneven_requests(seed=seed, n_requests=n_requests, n_choices=n_choices,
                               h_choices=h_choices, iters=100)
 
 

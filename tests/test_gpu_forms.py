@@ -39,29 +39,29 @@ def _run(req, iters, opts, samples=None, **kw):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp16", TOL_F16_TAIL), ("bf16", TOL_BF16_TAIL)])
-def test_reduced_forms_config1(prec, tol):
+def test_reduced_forms_white_batch(prec, tol):
     from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
     p = PREC_BF16 if prec == "bf16" else PREC_FP16
-    r = W.config1()
+    r = W.white_batch()
     x, rp, rd, it = _run(r, r.iters, options(precision=p, fp32_tail=10))
     O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
     err = np.abs(x - O.x).max()
     rel = err / np.abs(O.x).max()
-    print(f"config1 {prec}+10 fp32: max-abs {err:.3e} rel {rel:.3e}")
+    print(f"white_batch {prec}+10 fp32: max-abs {err:.3e} rel {rel:.3e}")
     assert err <= tol
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp16", TOL_F16_TAIL), ("bf16", TOL_BF16_TAIL)])
-def test_config3_full_size_sampled(prec, tol):
+def test_long_horizon_full_size_sampled(prec, tol):
     """N=8192, H=100, 12 joints, 100 iterations (90 reduced + 10 FP32); oracle on 24 samples."""
     from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16, PREC_FP32
     p = {"fp32": PREC_FP32, "fp16": PREC_FP16, "bf16": PREC_BF16}[prec]
-    r = W.config3()
+    r = W.long_horizon_batch()
     x, rp, rd, it = _run(r, r.iters, options(precision=p, fp32_tail=10))
     pick = np.unique(np.r_[np.arange(0, 8), np.arange(4096, 4104), np.arange(8184, 8192)])
     O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
     err = np.abs(x[pick] - O.x).max()
-    print(f"config3 {prec}: max-abs {err:.3e} rel {err / np.abs(O.x).max():.3e}")
+    print(f"long_horizon_batch {prec}: max-abs {err:.3e} rel {err / np.abs(O.x).max():.3e}")
     assert err <= tol
 
 
@@ -190,17 +190,17 @@ def _run_w(req, iters, opts, weights, samples=None, **kw):
     return r
 
 
-def test_block_weights_config2_sampled():
-    """Block penalty (1, 2.5/H, 4, 20), alpha 1.6, 100 iterations on config 2: FP32 parity."""
+def test_block_weights_mpc_batch_sampled():
+    """Block penalty (1, 2.5/H, 4, 20), alpha 1.6, 100 iterations on the 2048-sample H = 50 batch: FP32 parity."""
     from paper_2608_25666_amd import options
-    r = W.config2()
+    r = W.mpc_batch()
     x, rp, rd, it, w = _run_w(r, 100, options(alpha=1.6), W_DEF)
     assert w == (1.0, 0.05, 4.0, 20.0)
     pick = np.unique(np.r_[np.arange(0, 16), np.arange(2032, 2048)])
     O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=100,
                            alpha=1.6, weights=w)
     err = np.abs(x[pick] - O.x).max()
-    print(f"config2 weighted alpha 1.6: max-abs {err:.3e}")
+    print(f"mpc_batch weighted alpha 1.6: max-abs {err:.3e}")
     assert err <= 1e-4
     np.testing.assert_allclose(rp[pick], O.r_p, atol=1e-4, rtol=1e-3)
     np.testing.assert_allclose(rd[pick], O.r_d, atol=1e-4, rtol=1e-3)
@@ -259,8 +259,8 @@ def test_warm_start_advanced_by_one_step(alpha, weights):
     (x_warm = v_out, state_warm = state_out) gives the same bits."""
     import torch
     from paper_2608_25666_amd import Projector, options
-    from workloads import configs as WC
-    ctrl = WC.config5_controllers(seed=3, n_controllers=1)[0]
+    from workloads import recipes as WC
+    ctrl = WC.serving_controllers(seed=3, n_controllers=1)[0]
     H, nj, N = 30, 3, 40
     ctrl.H, ctrl.nj, ctrl.N = H, nj, N
     ctrl.freqs, ctrl.phases = ctrl.freqs[:nj], ctrl.phases[:nj]

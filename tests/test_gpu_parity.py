@@ -44,25 +44,25 @@ def check_residuals(rp, rd, O, sel=slice(None)):
     np.testing.assert_allclose(rd, O.r_d[sel], atol=1e-4, rtol=1e-3)
 
 
-def test_config1_fp32_matches_oracle():
-    r = W.config1()
+def test_white_batch_fp32_matches_oracle():
+    r = W.white_batch()
     x, rp, rd, it = gpu_solve(r, r.iters)
     O = admm.solve_request(r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
     err = np.abs(x - O.x).max()
-    print(f"config1 fp32 max-abs vs oracle: {err:.3e}")
+    print(f"white_batch fp32 max-abs vs oracle: {err:.3e}")
     assert err <= TOL_X
     check_residuals(rp, rd, O)
     assert np.all(it == r.iters)
 
 
-def test_config2_full_size_sampled_columns():
+def test_mpc_batch_full_size_sampled_columns():
     """N=2048, H=50 (not a multiple of 4), 12 joints, 100 iterations; oracle on 40 samples."""
-    r = W.config2()
+    r = W.mpc_batch()
     x, rp, rd, it = gpu_solve(r, r.iters)
     pick = np.unique(np.r_[np.arange(0, 24), np.arange(1000, 1008), np.arange(2032, 2048)])
     O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=r.iters)
     err = np.abs(x[pick] - O.x).max()
-    print(f"config2 fp32 max-abs vs oracle (sampled): {err:.3e}")
+    print(f"mpc_batch fp32 max-abs vs oracle (sampled): {err:.3e}")
     assert err <= TOL_X
     check_residuals(rp[pick], rd[pick], O)
 

@@ -16,13 +16,13 @@ import pytest
 
 from oracle import admm
 import workloads as W
-from workloads import configs as WC
+from workloads import recipes as WC
 
 pytestmark = pytest.mark.gpu
 
 
 def _controllers(seed, n, h_choices=(20, 50, 100, 33), n_choices=(16, 40, 64)):
-    cs = WC.config5_controllers(seed=seed, n_controllers=n, h_choices=h_choices,
+    cs = WC.serving_controllers(seed=seed, n_controllers=n, h_choices=h_choices,
                                 n_choices=n_choices)
     return cs
 

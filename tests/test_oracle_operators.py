@@ -54,7 +54,7 @@ def test_rows_match_time_stepping(H, dt):
 
 def test_violation_module_agrees_with_rows():
     """feasibility.violations (loops) and the row matrices flag the same violations."""
-    r = W.config1()
+    r = W.white_batch()
     x = r.samples.astype(np.float64)[:8]
     v = feasibility.violations(x, r.dt, r.bounds, r.q0, r.v0)
     for j in range(r.nj):

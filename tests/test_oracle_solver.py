@@ -145,7 +145,7 @@ def test_primal_step_solves_its_subproblem():
 
 def test_dual_residual_identity():
     """With alpha = 1, r_d equals rho ||C^T (z^L - z^{L-1})|| on rows 2..H."""
-    r = W.config1()
+    r = W.white_batch()
     j = 3
     lim = problem.joint_limits(r.bounds, j)
     rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
@@ -190,7 +190,7 @@ def test_joint_separability_against_stacked_problem():
 
 
 def test_grouped_early_exit():
-    r = W.config1()
+    r = W.white_batch()
     res = admm.solve_request(r.samples[:40], r.H, r.dt, r.bounds, r.q0, r.v0, iters=5000,
                              tol=1e-3, check_every=10)
     assert np.all(res.iters % 10 == 0)
@@ -240,7 +240,7 @@ def test_literal_iteration_stops_at_any_feasible_point():
 
 def test_kkt_factor_route_equals_reduced_inverse_route():
     """Iterating with x = K r + k v0 gives the same iterates as the LU solve of M."""
-    r = W.config1()
+    r = W.white_batch()
     j = 0
     lim = problem.joint_limits(r.bounds, j)
     rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])
@@ -305,7 +305,7 @@ def test_block_weighted_primal_step_solves_its_subproblem():
 
 def test_block_weighted_dual_residual_identity():
     """alpha = 1: r_d = ||C^T R (z^L - z^{L-1})|| on rows 2..H with the block penalty."""
-    r = W.config1()
+    r = W.white_batch()
     j = 2
     lim = problem.joint_limits(r.bounds, j)
     rows = problem.velocity_unit_rows(r.H, r.dt, lim, r.q0[j], r.v0[j])

@@ -14,7 +14,7 @@ generators stand in for the projection's inputs:
   i.i.d. N(0, 0.5^2) noise ("smooth").
 
 Every array is drawn from ``numpy.random.Generator(PCG64(seed))`` in a fixed
-order (q0, v0, base parameters, noise), so a (config, seed) pair names one input.
+order (q0, v0, base parameters, noise), so a (recipe, seed) pair names one input.
 Samples use the library's layout: float32 ``[N][H][n_joints]`` row-major.
 """
 
@@ -117,25 +117,25 @@ def make_request(seed: int, N: int, H: int, nj: int, dt: float, kind: str,
                    iters=iters, name=name)
 
 
-def config1(seed: int = 0) -> Request:
+def white_batch(seed: int = 0) -> Request:
     """12 joints, N=64, H=20, dt=0.05, white N(0,1) samples, rho=1, 200 iterations."""
     return make_request(seed, N=64, H=20, nj=12, dt=0.05, kind="white", sigma=1.0,
-                        iters=200, name="cfg1_N64_H20_J12_dt0.05")
+                        iters=200, name="white_N64_H20_J12_dt0.05")
 
 
-def config2(seed: int = 0, N: int = 2048) -> Request:
+def mpc_batch(seed: int = 0, N: int = 2048) -> Request:
     """12 joints, N=2048, H=50, dt=0.02, smooth base + N(0,0.5^2), rho=1, 100 iterations."""
     return make_request(seed, N=N, H=50, nj=12, dt=0.02, kind="smooth",
-                        iters=100, name=f"cfg2_N{N}_H50_J12_dt0.02")
+                        iters=100, name=f"mpc_N{N}_H50_J12_dt0.02")
 
 
-def config3(seed: int = 0, N: int = 8192) -> Request:
+def long_horizon_batch(seed: int = 0, N: int = 8192) -> Request:
     """12 joints, N=8192, H=100, dt=0.02, smooth generator, 100 iterations (90 reduced + 10 FP32)."""
     return make_request(seed, N=N, H=100, nj=12, dt=0.02, kind="smooth",
-                        iters=100, name=f"cfg3_N{N}_H100_J12_dt0.02")
+                        iters=100, name=f"long_N{N}_H100_J12_dt0.02")
 
 
-def config4_requests(seed: int = 0, n_requests: int = 64, n_choices=(128, 512, 2048, 4096),
+def uneven_requests(seed: int = 0, n_requests: int = 64, n_choices=(128, 512, 2048, 4096),
                      h_choices=(20, 50, 100), nj_choices=(6, 12), dt_choices=(0.02, 0.05),
                      iters: int = 100) -> List[Request]:
     """Uneven batch: each request draws H, N, joint count and dt uniformly, then its own inputs."""
@@ -146,7 +146,7 @@ def config4_requests(seed: int = 0, n_requests: int = 64, n_choices=(128, 512, 2
     reqs = []
     for r, (H, N, nj, dt) in enumerate(shapes):
         reqs.append(make_request(seed * 1000 + r + 1, N=N, H=H, nj=nj, dt=dt, kind="smooth",
-                                 iters=iters, name=f"cfg4_r{r}_N{N}_H{H}_J{nj}_dt{dt}"))
+                                 iters=iters, name=f"uneven_r{r}_N{N}_H{H}_J{nj}_dt{dt}"))
     return reqs
 
 
@@ -167,7 +167,7 @@ class Controller:
     v0: np.ndarray
 
 
-def config5_controllers(seed: int = 0, n_controllers: int = 32, rate_hz: float = 20.0,
+def serving_controllers(seed: int = 0, n_controllers: int = 32, rate_hz: float = 20.0,
                         duration_s: float = 60.0, n_choices=(128, 512, 2048, 4096),
                         h_choices=(20, 50, 100), nj_choices=(6, 12),
                         dt_choices=(0.02, 0.05)) -> List[Controller]:
