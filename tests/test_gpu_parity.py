@@ -179,3 +179,51 @@ def test_infeasible_boundary_rejected():
     with pytest.raises(PrismError) as e:
         P.solve(x, r.q0, bad, 10)
     assert e.value.status == -4
+
+
+def test_bench_launch_configuration_sampled_groups():
+    """The launch bench.py times: 2048 samples x 12 joints, H = 50, block weights
+    (1, 0.05, 4, 20), alpha 1.6, residual <= 1e-3 checked every 10. Sampled groups
+    (samples 0-31 and 2016-2047, every joint) against the oracle at the same settings:
+    stop counts equal or one check period apart (FP32 vs FP64 deciding a comparison
+    within rounding of the tolerance), x equal at the FP32 bar where the counts agree."""
+    import torch
+    from paper_2608_25666_amd import Projector, options
+    r = W.mpc_batch()
+    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+    x = torch.from_numpy(r.samples).cuda()
+    it = torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda")
+    out, rp, rd = P.solve(x, r.q0, r.v0, 20000, opts=options(alpha=1.6, tol=1e-3), iters_out=it)
+    torch.cuda.synchronize()
+    xg, itg = out.cpu().numpy(), it.cpu().numpy()
+    res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+    assert np.all(res <= 1e-3)
+    pick = np.r_[np.arange(0, 32), np.arange(2016, 2048)]
+    O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=20000,
+                           tol=1e-3, check_every=10, alpha=1.6, weights=P.weights)
+    d = np.abs(itg[pick] - O.iters)
+    print(f"stop counts: gpu {np.unique(itg[pick])} oracle {np.unique(O.iters)}; "
+          f"{(d == 0).mean():.2f} equal")
+    assert np.all((d == 0) | (d == 10))
+    assert (d == 0).mean() >= 0.8
+    same = (d == 0).all(axis=1)
+    np.testing.assert_allclose(xg[pick][same], O.x[same], atol=1e-4)
+    P.close()
+
+
+def test_maximum_joints_and_a_large_batch():
+    """64 joints (the ABI maximum) and 4096 samples (16384 tiles): sampled FP32 parity."""
+    import torch
+    from paper_2608_25666_amd import Projector, options
+    r = W.make_request(51, N=4096, H=30, nj=64, dt=0.02, kind="smooth")
+    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+    x = torch.from_numpy(r.samples).cuda()
+    out, _, _ = P.solve(x, r.q0, r.v0, 80, opts=options(alpha=1.6))
+    torch.cuda.synchronize()
+    pick = np.r_[0, 1, 2047, 4094, 4095]
+    O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=80,
+                           alpha=1.6, weights=P.weights)
+    err = np.abs(out.cpu().numpy()[pick] - O.x).max()
+    print(f"64 joints x 4096 samples: max-abs {err:.3e}")
+    assert err <= 1e-4
+    P.close()
