@@ -85,9 +85,29 @@ def build(jobs: int = 0, incremental: bool = False, verbose: bool = False) -> st
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_abi_consumer(verbose)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f} s", flush=True)
     return LIB
+
+
+ABI_DEMO_SRC = os.path.join(os.path.dirname(PKG), "tests", "cpp", "abi_solve.cpp")
+ABI_DEMO = os.path.join(os.path.dirname(PKG), "tests", "cpp", "abi_solve")
+
+
+def build_abi_consumer(verbose: bool = False):
+    """The native C-ABI consumer used by the tests (host program linking the library)."""
+    if not os.path.exists(ABI_DEMO_SRC):
+        return None
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-I", INCLUDE, ABI_DEMO_SRC,
+           "-L", PKG, "-lprism_proj", f"-Wl,-rpath,{PKG}", "-Wl,-rpath,$ORIGIN/../../paper_2608_25666_amd",
+           "-o", ABI_DEMO]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building {ABI_DEMO_SRC} failed:\n{r.stderr}")
+    if verbose:
+        print(f"built {ABI_DEMO}", flush=True)
+    return ABI_DEMO
 
 
 def main(argv=None):
