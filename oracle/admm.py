@@ -258,13 +258,14 @@ def advance_warm_start(x: np.ndarray, y: np.ndarray, z: np.ndarray, H: int, v0_n
 
 def literal_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
                   q0: float, v0: float, delta: float = 1.0, iters: int = 100,
-                  x_init: Optional[np.ndarray] = None, lam_init: Optional[np.ndarray] = None):
+                  x_init: Optional[np.ndarray] = None, lam_init: Optional[np.ndarray] = None,
+                  return_lam: bool = False):
     """Sec. III-D, eqs. (admm_zeta), (admm_primal)/(admm_KKT), (admm_dual), verbatim.
 
     G, h in the paper's physical scaling (eq. (G_h_def), one joint), penalty delta,
     lambda in the primal space, lambda_0 = 0 and x_0 = x~ with x_1 := v0 unless
     ``lam_init`` / ``x_init`` are given. Returns (x (ncols, H), max constraint
-    violation per column).
+    violation per column), and lambda (ncols, H) as a third item with ``return_lam``.
     """
     G, h = problem.per_joint_G_h(H, dt, lim, q0, v0)
     fac = KKTFactor(np.eye(H) + delta * (G.T @ G))
@@ -278,4 +279,6 @@ def literal_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimi
         x = fac.solve(delta * (G.T @ (hh - zeta)) + lam + xt, v0)           # Step 2
         lam = lam - 0.5 * delta * (G.T @ (G @ x - hh + zeta))               # Step 3
     viol = np.maximum(0.0, np.max(G @ x - hh, axis=0))
+    if return_lam:
+        return x.T.copy(), viol, lam.T.copy()
     return x.T.copy(), viol

@@ -370,3 +370,68 @@ def test_advance_warm_start_keeps_a_stationary_solution(alpha):
                         warm_x=xs[:, :, 0], warm_y=ys[:, 0], warm_z=zs[:, 0], **kw)
     assert np.all(b.iters == 0)
     np.testing.assert_allclose(b.x, a.x, atol=1e-9)
+
+
+def _aug_lag(x, xt, lam, zeta, G, h, delta):
+    """Eq. (aug_lag) as a scalar, one column."""
+    r = G @ x - h + zeta
+    return 0.5 * np.sum((x - xt) ** 2) - lam @ x + 0.5 * delta * (r @ r)
+
+
+@pytest.mark.parametrize("delta", [1.0, 0.05])
+def test_literal_primal_step_minimizes_the_augmented_objective(delta):
+    """One printed pass from (x~ with x_1 := v0, lambda = 0): the returned x has x_1 = v0
+    and zero gradient of the scalar eq. (aug_lag) in every free step (central
+    differences, exact for a quadratic up to rounding), with zeta = max(0, h - G x0)."""
+    rng = np.random.default_rng(31)
+    H, dt = 7, 0.05
+    lim = _lim()
+    q0, v0 = 0.1, 0.3
+    xt = rng.normal(0, 2, (3, H))
+    x1, _, lam1 = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=delta, iters=1,
+                                     return_lam=True)
+    G, h = problem.per_joint_G_h(H, dt, lim, q0, v0)
+    for c in range(3):
+        x0 = xt[c].copy()
+        x0[0] = v0
+        zeta = np.maximum(0.0, h - G @ x0)
+        assert abs(x1[c, 0] - v0) <= 1e-12
+        scale = 1.0 + delta * np.abs(G).max() ** 2 * np.abs(x1[c]).max()
+        for k in range(1, H):
+            e = np.zeros(H)
+            e[k] = 1e-3
+            gk = (_aug_lag(x1[c] + e, xt[c], np.zeros(H), zeta, G, h, delta)
+                  - _aug_lag(x1[c] - e, xt[c], np.zeros(H), zeta, G, h, delta)) / 2e-3
+            assert abs(gk) <= 1e-7 * scale, (c, k, gk)
+
+
+def test_literal_multiplier_step_closed_form():
+    """With the dual step delta/2 of eq. (admm_dual) and an exact primal step, the
+    stationarity of Step 2 turns Step 3 into lambda' = (lambda + x' - x~) / 2 on every
+    free step (steps 2..H): a closed form that a wrong dual step size or sign breaks."""
+    rng = np.random.default_rng(32)
+    H, dt = 9, 0.05
+    lim = _lim()
+    q0, v0 = -0.1, -0.2
+    xt = rng.normal(0, 2, (4, H))
+    lam0 = rng.normal(0, 0.5, (4, H))
+    for delta in (1.0, 0.3):
+        x1, _, lam1 = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=delta, iters=1,
+                                         lam_init=lam0, return_lam=True)
+        want = 0.5 * (lam0 + x1 - xt)
+        np.testing.assert_allclose(lam1[:, 1:], want[:, 1:], atol=1e-7, rtol=1e-9)
+
+
+def test_literal_feasible_sample_is_a_fixed_point():
+    """A feasible sample with x~_1 = v0 has zeta = h - G x~, so the primal step returns it
+    and the multiplier stays zero: unchanged after any number of passes."""
+    H, dt = 12, 0.05
+    lim = _lim()
+    q0, v0 = 0.0, 0.2
+    xt = np.stack([np.full(H, v0), v0 + 0.01 * np.sin(np.arange(H))])
+    xt[:, 0] = v0
+    G, h = problem.per_joint_G_h(H, dt, lim, q0, v0)
+    assert np.all(G @ xt.T <= h[:, None])
+    x, viol = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=1.0, iters=50)
+    np.testing.assert_allclose(x, xt, atol=1e-12)
+    assert np.all(viol == 0.0)
