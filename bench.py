@@ -55,6 +55,9 @@ PEAK_MFMA_B16_TFLOPS = 2500.0
 # FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations per second
 # (one add/sub/max/med3/fma per lane per cycle; packed FP32 is not used).
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP64: dense matrix 78.6 TFLOP/s; vector FP64 issues at the same lane rate as FP32
+# (78.6 TFLOP/s counting an FMA as two), so PEAK_VALU_TOPS lane operations per second.
+PEAK_MFMA_F64_TFLOPS = 78.6
 
 
 def valu_ops_per_col_iter(H: int) -> float:
@@ -71,6 +74,18 @@ def valu_ops_per_col_iter(H: int) -> float:
 def mfma_flops_per_col_iter(H: int) -> float:
     """x += K d with the nonzero (H-1) x (H-1) block of K."""
     return 2.0 * (H - 1) ** 2
+
+
+def literal_valu_ops_per_col_pass(H: int) -> float:
+    """Algorithmic FP64 vector operations of one printed Bregman pass on one column.
+
+    Rows s = C x at x: position prefix sums, acceleration and jerk differences (3H).
+    Step 1 and the right-hand side of Step 2 in row form: m = min(ub, s) + max(lb, s)
+    on 4H-1 rows (3 each); C^T W m: position suffix sums (H), one weighted
+    accumulation per row into its step (4H), acceleration/jerk stencils (3H); rhs and
+    t = w + delta/2 u (2H). Step 3: rows at x' (3H), C^T W s' (8H), w update (H).
+    """
+    return 3 * H + 3 * (4 * H - 1) + 8 * H + 2 * H + 3 * H + 8 * H + H
 
 
 def parse():
@@ -94,7 +109,9 @@ def parse():
                     help="skip the fixed-100-iteration section (for single-mode profiles)")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
     ap.add_argument("--workload", default="mpc",
-                    choices=["mpc", "long", "uneven", "serve", "sigma", "plan"])
+                    choices=["mpc", "long", "uneven", "serve", "sigma", "plan", "literal"])
+    ap.add_argument("--passes", type=int, default=20, help="literal: printed Bregman passes")
+    ap.add_argument("--delta", type=float, default=1.0, help="literal: penalty delta")
     ap.add_argument("--sigma", type=float, default=1.0, help="sigma: sampling sigma")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     ap.add_argument("--controllers", type=int, default=32, help="serve: controllers")
@@ -114,21 +131,26 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_sha() -> str:
-    """sha256 over the kernel sources (csrc/*.h and admm_*.hip), as recorded beside the
-    rocprofv3 counters in profiles/traffic.json."""
+def kernel_source_sha(literal: bool = False) -> str:
+    """sha256 over the device sources of a kernel, as recorded beside the rocprofv3
+    counters in profiles/traffic.json: kernel_args.h with admm_*.h and admm_*.hip for
+    the projection kernels, kernel_args.h with literal.hip for the printed iteration."""
     import hashlib
     d = os.path.join(ROOT, "paper_2608_25666_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith(".h") or (f.startswith("admm_") and f.endswith(".hip")):
+        if literal:
+            own = f in ("kernel_args.h", "literal.hip")
+        else:
+            own = f == "kernel_args.h" or (f.startswith("admm_") and f[-2:] in (".h", "ip"))
+        if own:
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, sha: str = None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None
     when none were taken for this workload or the kernel sources changed since."""
     try:
@@ -136,7 +158,7 @@ def measured_traffic(key: str):
             t = json.load(fh).get(key)
     except (OSError, ValueError):
         return None
-    if not t or t.get("source_sha256") != kernel_source_sha():
+    if not t or t.get("source_sha256") != (sha or kernel_source_sha()):
         return None
     return 1024.0 * (t["fetch_kib_per_dispatch"] * t["fetch_factor"] +
                      t["write_kib_per_dispatch"] * t["write_factor"])
@@ -563,6 +585,84 @@ def run_plan(a):
     print(json.dumps(line), flush=True)
 
 
+def run_literal(a):
+    """The printed Bregman iteration (fast feasible-sample mode, not the projection) on
+    the default batch shape: a fixed number of FP64 passes."""
+    import ctypes as C
+    import torch
+    import workloads as W
+    from paper_2608_25666_amd import Projector, _lib as L
+    req = W.mpc_batch(N=a.N)
+    H, nj, N = req.H, req.nj, req.N
+    P = Projector(H, nj, req.dt, req.bounds, req.rho, weights="default")
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(req.samples).to(dev)
+    out = torch.empty_like(x)
+    viol = torch.empty((N, nj), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    # arguments marshalled once, so the timed loop is the launch alone
+    q0a = L.dbl_array(np.asarray(req.q0, dtype=np.float64))
+    v0a = L.dbl_array(np.asarray(req.v0, dtype=np.float64))
+    la = L.LiteralArgs()
+    la.v_samples, la.x_init, la.v_out, la.violation = x.data_ptr(), None, out.data_ptr(), viol.data_ptr()
+    la.N, la.iters, la.delta = N, a.passes, a.delta
+    la.q0 = C.cast(q0a, C.POINTER(C.c_double))
+    la.v0 = C.cast(v0a, C.POINTER(C.c_double))
+    fn, h, sp = L.lib().prism_proj_literal, P.handle, C.c_void_p(stream.cuda_stream)
+
+    def step():
+        st = fn(h, C.byref(la), sp)
+        if st != 0:
+            L.check(st, "prism_proj_literal")
+
+    wall, per = _timed(step, a.steps, a.warmup, stream)
+    kern_s = float(per.mean()) * 1e-3
+    colp = float(N) * nj * a.passes
+    mflop = 2.0 * (H - 1) ** 2 * colp
+    valu = literal_valu_ops_per_col_pass(H) * colp
+    t_m = mflop / (PEAK_MFMA_F64_TFLOPS * 1e12)
+    t_v = valu / (PEAK_VALU_TOPS * 1e12)
+    if t_m >= t_v:
+        ach = mflop / kern_s / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_F64_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_F64_TFLOPS}
+    else:
+        ach = valu / kern_s / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_VALU_TOPS}
+    roof["traffic"] = measured_traffic(f"literal_N{N}_H{H}_J{nj}_{a.passes}passes",
+                                       sha=kernel_source_sha(literal=True))
+    roof["algorithmic_bytes"] = 2 * N * H * nj * 4 + N * nj * 8
+    roof["valu_frac"] = valu / kern_s / 1e12 / PEAK_VALU_TOPS
+    roof["mfma_frac"] = mflop / kern_s / 1e12 / PEAK_MFMA_F64_TFLOPS
+    v = viol.cpu().numpy()
+    line = {"metric": f"trajectories/sec through {a.passes} printed Bregman passes "
+                      "(fast feasible-sample mode, not the projection)",
+            "value": N / (wall / a.steps), "unit": "trajectories/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall * 1e3 / a.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"printed Bregman iteration: {N} samples x {nj} joints, "
+                                   f"H={H}, dt={req.dt}, {a.passes} passes, delta={a.delta:g}, "
+                                   "FP64"},
+            "kernel_ms": float(per.mean()),
+            "violation": {"max": float(v.max()), "frac_le_1e-3": float(np.mean(v <= 1e-3))},
+            "roofline": roof}
+    if not a.no_cpu_baseline:
+        from oracle import admm, problem
+        t0 = time.perf_counter()
+        for j in range(nj):
+            admm.literal_joint(req.samples[:, :, j].astype(np.float64), H, req.dt,
+                               problem.joint_limits(req.bounds, j), float(req.q0[j]),
+                               float(req.v0[j]), delta=a.delta, iters=a.passes)
+        dt_cpu = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": N / dt_cpu, "unit": "trajectories/s",
+                                "cores": _oracle_threads(), "kind": "oracle",
+                                "sample": f"the whole batch ({N} samples x {nj} joints), "
+                                          f"oracle literal_joint, {dt_cpu:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -591,6 +691,8 @@ def main():
         return run_sigma(a)
     if a.workload == "plan":
         return run_plan(a)
+    if a.workload == "literal":
+        return run_literal(a)
     prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
     req = W.long_horizon_batch() if a.workload == "long" else W.mpc_batch(N=a.N)
     dev = torch.device("cuda:0")

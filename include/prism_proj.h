@@ -305,6 +305,52 @@ size_t prism_plan_workspace_bytes(int H, int n_joints, int N);
  * must be ordered (same stream). */
 prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * prism_proj_literal -- the Bregman iteration exactly as Sec. III-D prints it
+ * (eqs. (admm_zeta), (admm_primal)/(admm_KKT), (admm_dual)), a fixed number of
+ * passes in FP64. NOT the projection: the multiplier lambda is kept in the
+ * primal space and the slack step does not see it, so every feasible x with
+ * lambda = x - x~ is a fixed point; the passes stop at a feasible trajectory
+ * near the sample, not at the nearest one. This is the fast mode behind the
+ * paper's remark that ten to twenty iterations suffice (Sec. III-D
+ * "Convergence"); prism_proj_solve is the projection.
+ *
+ * Per (sample, joint) column, with G = [C; -C] and h in the paper's physical
+ * row scaling (eq. (G_h_def)), penalty delta, lambda_0 = 0 and
+ * x_0 = x_init (or the sample) with its first step set to v0:
+ *   zeta'   = max(0, h - G x)
+ *   x'      = argmin of eq. (aug_lag) in x subject to x_1 = v0, i.e.
+ *             (I + delta G^T G) x' + A^T mu = x~ + lambda + delta G^T (h - zeta')
+ *   lambda' = lambda - (delta/2) G^T (G x' - h + zeta').
+ * The handle supplies H, dt, the bounds and the device; its options and block
+ * weights are not used. The factor of I + delta G^T G is built on the host on
+ * the first call with a given delta (one device allocation and a blocking copy,
+ * on the calling thread) and kept until prism_proj_destroy; at most 64
+ * distinct deltas per handle (PRISM_ENOMEM beyond).
+ * Arithmetic is FP64 throughout (samples are widened on load, x is rounded to
+ * FP32 on store). v_out may equal v_samples or x_init.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* v_samples;   /* device [N][H][n_joints]: x~                                */
+  const float* x_init;      /* device [N][H][n_joints] or NULL: first iterate (x~ if NULL) */
+  float* v_out;             /* device [N][H][n_joints]: the iterate after `iters` passes   */
+  double* violation;        /* device [N][n_joints] or NULL: largest bound violation of
+                               that iterate over all rows of G x <= h, in each row's own
+                               physical unit (rad, rad/s, rad/s^2, rad/s^3), >= 0          */
+  int32_t N;                /* samples, >= 0 (0: nothing enqueued)                         */
+  int32_t iters;            /* passes, >= 0                                                */
+  double delta;             /* penalty of eq. (aug_lag), > 0 and finite                    */
+  const double* q0;         /* host [n_joints]                                             */
+  const double* v0;         /* host [n_joints]                                             */
+} prism_literal_args_t;
+
+/* Enqueues the passes on `stream`. PRISM_EINVAL (null pointer, N < 0, iters < 0,
+ * delta not positive), PRISM_EINFEASIBLE (as prism_proj_solve), PRISM_EDEVICE
+ * (wrong device current, launch failure), PRISM_ENOMEM (factor allocation);
+ * nothing is enqueued on error. */
+prism_status_t prism_proj_literal(prism_proj_t p, const prism_literal_args_t* a,
+                                  hipStream_t stream);
+
 /* prism_proj_feasibility -- FP64 final check of trajectories (device kernel).
  * For each column writes to viol (device, float64 [N][n_joints][5]) the largest
  * violation of the position (rad), velocity (rad/s), acceleration (rad/s^2)

@@ -72,6 +72,13 @@ class PlanArgs(C.Structure):
                 ("opts", C.POINTER(Options))]
 
 
+class LiteralArgs(C.Structure):
+    _fields_ = [("v_samples", C.c_void_p), ("x_init", C.c_void_p), ("v_out", C.c_void_p),
+                ("violation", C.c_void_p), ("N", C.c_int32), ("iters", C.c_int32),
+                ("delta", C.c_double), ("q0", C.POINTER(C.c_double)),
+                ("v0", C.POINTER(C.c_double))]
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
                 ("max_queue", C.c_int32), ("grid_share", C.c_int32), ("opts", Options)]
@@ -148,6 +155,7 @@ def load(path: str = LIB_PATH):
                                         C.c_void_p]),
         "prism_plan_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
         "prism_plan_step": (st, [H, C.POINTER(PlanArgs), C.c_void_p]),
+        "prism_proj_literal": (st, [H, C.POINTER(LiteralArgs), C.c_void_p]),
         "prism_server_config_default": (None, [C.POINTER(ServerConfig)]),
         "prism_server_create": (st, [C.POINTER(ServerConfig), C.POINTER(H)]),
         "prism_server_destroy": (None, [H]),

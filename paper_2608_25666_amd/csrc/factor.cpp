@@ -114,6 +114,13 @@ inline int out_row(int b, int m, int HQ, int H) {
   return (reg < HQ && row < H) ? row : -1;
 }
 
+// The same for the FP64 accumulator (row m of a block is lane group m%4, item m/4).
+inline int out_row_f64(int b, int m, int HQ, int H) {
+  const int reg = 4 * b + (m >> 2);
+  const int row = (m & 3) * HQ + reg;
+  return (reg < HQ && row < H) ? row : -1;
+}
+
 inline int in_row(int gk, int j, int HQ, int H) {
   const int row = gk * HQ + j;
   return (j < HQ && row < H) ? row : -1;
@@ -163,6 +170,23 @@ void layout_16(const std::vector<double>& K, int H, int HQ, bool bf16, std::vect
           const float v = (r >= 0 && c >= 0) ? (float)K[(size_t)r * H + c] : 0.0f;
           out[(((size_t)b * nj8 + jj) * 64 + lane) * 8 + e] =
               bf16 ? float_to_bf16_rne(v) : float_to_f16_rne(v);
+        }
+}
+
+void layout_f64(const std::vector<double>& K, const std::vector<double>& k, int H, int HQ,
+                std::vector<double>& out) {
+  const int nb = (HQ + 3) / 4, nj2 = (HQ + 1) / 2;
+  out.assign(f64_frag_count(HQ), 0.0);
+  for (int b = 0; b < nb; ++b)
+    for (int jp = 0; jp < nj2; ++jp)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 2; ++e) {
+          const int r = out_row_f64(b, lane & 15, HQ, H);
+          const int c = in_row(lane >> 4, 2 * jp + e, HQ, H);
+          // column 0 of K is zero (step 1 is pinned); it carries k instead, so
+          // x = K' r with r_1 := v0
+          const double v = c == 0 ? k[r] : K[(size_t)r * H + c];
+          out[(((size_t)b * nj2 + jp) * 64 + lane) * 2 + e] = (r >= 0 && c >= 0) ? v : 0.0;
         }
 }
 

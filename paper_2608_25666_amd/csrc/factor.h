@@ -28,6 +28,19 @@ void layout_f32(const std::vector<double>& K, int H, int HQ, std::vector<float>&
 // NJ8 = ceil(HQ/8). bf16 = true selects bfloat16, otherwise IEEE half. RNE.
 void layout_16(const std::vector<double>& K, int H, int HQ, bool bf16, std::vector<uint16_t>& out);
 
+// FP64 A-operand fragments for v_mfma_f64_16x16x4_f64, whose accumulator puts
+// row g + 4e of a 16x16 block in item e of lane group g (the FP32 form uses
+// row 4g + e). Two k-steps per lane per (output block b, pair jp), read as one
+// 16-byte load: index ((b * NJ2 + jp) * 64 + lane) * 2 + e, k-step j = 2*jp + e,
+// NB = ceil(HQ/4), NJ2 = ceil(HQ/2). Column 0 of K (identically zero: step 1 is
+// fixed by the equality) holds k instead, so that x = K r + k v0 is one product
+// with r_1 set to v0.
+void layout_f64(const std::vector<double>& K, const std::vector<double>& k, int H, int HQ,
+                std::vector<double>& out);
+inline size_t f64_frag_count(int HQ) {
+  return (size_t)((HQ + 3) / 4) * ((HQ + 1) / 2) * 64 * 2;
+}
+
 // Byte sizes of the two layouts.
 inline size_t f32_frag_bytes(int HQ) {
   const int nb = (HQ + 3) / 4;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "admm_kernels.h"
@@ -26,9 +28,14 @@ struct prism_proj_s {
   int* d_counters = nullptr;        // ring of tile counters for early-exit solves
   std::atomic<unsigned> next_counter{0};
   int f32_bytes = 0, b16_bytes = 0;
+  std::mutex lit_mu;                              // guards lit
+  std::vector<std::pair<double, double*>> lit;    // device factors of the printed iteration, per delta
 };
 
 namespace prism {
+
+// Frees the printed iteration's device factors of a handle.
+void release_literal_factors(prism_proj_s* p);
 
 // Row bounds of every joint for boundary values (q0, v0); PRISM_EINFEASIBLE if
 // the first rows (fixed by x_1 = v0) cannot hold.

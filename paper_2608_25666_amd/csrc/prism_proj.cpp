@@ -323,6 +323,7 @@ void prism_proj_destroy(prism_proj_t p) {
   if (p->frag_f16) (void)hipFree(p->frag_f16);
   if (p->d_bounds) (void)hipFree(p->d_bounds);
   if (p->d_counters) (void)hipFree(p->d_counters);
+  release_literal_factors(p);
   delete p;
 }
 

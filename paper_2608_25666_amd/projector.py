@@ -142,6 +142,39 @@ class Projector:
                 "prism_proj_solve_ex")
         return out, r_primal, r_dual
 
+    def literal(self, samples, q0, v0, iters: int, delta: float = 1.0, x_init=None, out=None,
+                violation=None, stream=None):
+        """The Bregman iteration as Sec. III-D prints it (prism_proj_literal), FP64:
+        `iters` passes from x_init (or the samples), lambda_0 = 0. Not the
+        projection: it stops at a feasible point near the sample. Asynchronous on
+        the stream. Returns (v_out [N][H][nj] float32, violation [N][nj] float64)."""
+        import torch
+        N = int(samples.shape[0])
+        assert samples.dtype == torch.float32 and samples.is_cuda and samples.is_contiguous()
+        assert tuple(samples.shape[1:]) == (self.H, self.nj)
+        if x_init is not None:
+            assert x_init.dtype == torch.float32 and x_init.is_contiguous()
+            assert x_init.shape == samples.shape
+        if out is None:
+            out = torch.empty_like(samples)
+        if violation is None:
+            violation = torch.empty((N, self.nj), dtype=torch.float64, device=samples.device)
+        q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
+        v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
+        a = L.LiteralArgs()
+        a.v_samples = samples.data_ptr()
+        a.x_init = None if x_init is None else x_init.data_ptr()
+        a.v_out = out.data_ptr()
+        a.violation = violation.data_ptr()
+        a.N = N
+        a.iters = int(iters)
+        a.delta = float(delta)
+        a.q0 = C.cast(q0a, C.POINTER(C.c_double))
+        a.v0 = C.cast(v0a, C.POINTER(C.c_double))
+        L.check(L.lib().prism_proj_literal(self._h, C.byref(a), _stream(stream)),
+                "prism_proj_literal")
+        return out, violation
+
     def plan_step(self, nu, sigma, N: int, seed: int, stream_id: int, q0, v0, theta_ref,
                   w_pos: float, w_vel: float, tau: float, eps: float, iters: int,
                   opts: Optional[L.Options] = None, samples_out=None, r_primal=None,

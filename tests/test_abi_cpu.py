@@ -119,6 +119,8 @@ def test_null_handle_calls_are_rejected():
     assert lib.prism_proj_solve(None, None, 0, None, None, 0, None, None, None, None) == L.PRISM_EINVAL
     a = L.SolveArgs()
     assert lib.prism_proj_solve_ex(None, C.byref(a), None) == L.PRISM_EINVAL
+    la = L.LiteralArgs()
+    assert lib.prism_proj_literal(None, C.byref(la), None) == L.PRISM_EINVAL
     assert lib.prism_proj_horizon(None) == -1
     lib.prism_proj_destroy(None)
     assert lib.prism_factor_host(1, 1.0, None, None, None) == L.PRISM_EINVAL
