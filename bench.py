@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--alpha", type=float, default=1.6)
+    ap.add_argument("--alpha", type=float, default=1.8)
     ap.add_argument("--weights", default="default", choices=["default", "unit"],
                     help="block penalty weights: prism_default_block_weights(H) or all ones")
     ap.add_argument("--tol", type=float, default=1e-3)

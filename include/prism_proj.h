@@ -130,7 +130,8 @@ prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bou
 prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_bounds_t* bounds,
                                     double rho, const double* block_weights, prism_proj_t* out);
 
-/* Recommended block weights for horizon H: (1, 2.5/H, 4, 20). Writes w[0..3]. */
+/* Recommended block weights for horizon H, for rho = 1 and alpha = 1.8:
+ * (1.7, 2.125/H, 13.6, 17). Writes w[0..3]. */
 void prism_default_block_weights(int H, double* w);
 
 /* Set the handle's default options (used by prism_proj_solve). Not safe to

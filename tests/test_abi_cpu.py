@@ -102,7 +102,7 @@ def test_default_block_weights_and_weight_validation():
     L, lib = _lib()
     w = (C.c_double * 4)()
     lib.prism_default_block_weights(50, w)
-    assert tuple(w) == (1.0, 0.05, 4.0, 20.0)
+    assert tuple(w) == (1.7, 2.125 / 50, 13.6, 17.0)
     b, keep = _bounds(2)
     h = C.c_void_p()
     bad = (C.c_double * 4)(1.0, 0.0, 1.0, 1.0)

@@ -15,7 +15,7 @@ Stated tolerances (rad/s, max-abs against the FP64 oracle at the same count):
 import numpy as np
 import pytest
 
-from oracle import admm
+from oracle import admm, problem
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -191,19 +191,27 @@ def _run_w(req, iters, opts, weights, samples=None, **kw):
 
 
 def test_block_weights_mpc_batch_sampled():
-    """Block penalty (1, 2.5/H, 4, 20), alpha 1.6, 100 iterations on the 2048-sample H = 50 batch: FP32 parity."""
+    """Default block penalty (1.7, 2.125/H, 13.6, 17), alpha 1.8, 100 iterations on the
+    2048-sample H = 50 batch: FP32 parity."""
     from paper_2608_25666_amd import options
     r = W.mpc_batch()
-    x, rp, rd, it, w = _run_w(r, 100, options(alpha=1.6), W_DEF)
-    assert w == (1.0, 0.05, 4.0, 20.0)
+    x, rp, rd, it, w = _run_w(r, 100, options(alpha=1.8), W_DEF)
+    assert w == (1.7, 2.125 / 50, 13.6, 17.0)
     pick = np.unique(np.r_[np.arange(0, 16), np.arange(2032, 2048)])
     O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=100,
-                           alpha=1.6, weights=w)
+                           alpha=1.8, weights=w)
     err = np.abs(x[pick] - O.x).max()
-    print(f"mpc_batch weighted alpha 1.6: max-abs {err:.3e}")
+    # r_d is a difference of terms as large as (|C|^T |y|)_k; the FP32 multiplier
+    # accumulates rounding on them over the iterations (random walk: sqrt(L) roundings)
+    C = np.abs(problem.velocity_unit_rows(r.H, r.dt, problem.joint_limits(r.bounds, 0),
+                                          r.q0[0], r.v0[0]).C)
+    big = np.einsum("rk,njr->njk", C, np.abs(O.y))[:, :, 1:].max()
+    rd_bar = 1e-4 + np.sqrt(100) * 2.0 ** -24 * big
+    print(f"mpc_batch weighted alpha 1.8: max-abs {err:.3e}; r_d max diff "
+          f"{np.abs(rd[pick] - O.r_d).max():.2e} (bar {rd_bar:.2e}, |C|^T|y| {big:.0f})")
     assert err <= 1e-4
     np.testing.assert_allclose(rp[pick], O.r_p, atol=1e-4, rtol=1e-3)
-    np.testing.assert_allclose(rd[pick], O.r_d, atol=1e-4, rtol=1e-3)
+    np.testing.assert_allclose(rd[pick], O.r_d, atol=rd_bar, rtol=1e-3)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
