@@ -1,6 +1,7 @@
 // Host-side construction of the reusable x-update factor and its on-chip layouts.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
