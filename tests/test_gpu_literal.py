@@ -141,3 +141,22 @@ def test_literal_errors_and_empty():
     torch.cuda.synchronize()
     assert o.shape == (0, 20, 2) and v.shape == (0, 2)
     P.close()
+
+
+def test_literal_very_large_batch_sampled():
+    """131072 samples x 12 joints (98304 tiles), 10 passes: sampled outputs against the
+    oracle run on those samples alone (columns are independent)."""
+    import torch
+    from paper_2608_25666_amd import Projector
+    req = WC.make_request(53, N=131072, H=20, nj=12, dt=0.05, kind="white")
+    P = Projector(req.H, req.nj, req.dt, req.bounds, 1.0, weights="default")
+    x = torch.from_numpy(req.samples).cuda()
+    o, viol = P.literal(x, req.q0, req.v0, 10, delta=1.0)
+    torch.cuda.synchronize()
+    pick = np.r_[0, 1, 65535, 65536, 131070, 131071]
+    xg, vg = o.cpu().numpy()[pick], viol.cpu().numpy()[pick]
+    P.close()
+    sub = WC.Request(H=req.H, nj=req.nj, dt=req.dt, bounds=req.bounds, q0=req.q0, v0=req.v0,
+                     samples=np.ascontiguousarray(req.samples[pick]), rho=1.0, iters=10, name="")
+    xo, vo = _run_oracle(sub, 10, 1.0)
+    _check(sub, xg, vg, xo, vo, "131072 x 12, sampled", 10, 1.0)

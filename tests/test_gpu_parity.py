@@ -227,3 +227,24 @@ def test_maximum_joints_and_a_large_batch():
     print(f"64 joints x 4096 samples: max-abs {err:.3e}")
     assert err <= 1e-4
     P.close()
+
+
+def test_very_large_batch_sampled():
+    """131072 samples x 12 joints (98304 tiles, every tile counter and queue index far
+    beyond the benchmarks): sampled FP32 parity at a fixed count, first, middle and last
+    samples, and the last sample block's ragged-free tail."""
+    import torch
+    from paper_2608_25666_amd import Projector, options
+    r = W.make_request(52, N=131072, H=20, nj=12, dt=0.05, kind="white")
+    P = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+    x = torch.from_numpy(r.samples).cuda()
+    out, rp, _ = P.solve(x, r.q0, r.v0, 40, opts=options(alpha=1.8))
+    torch.cuda.synchronize()
+    pick = np.r_[0, 1, 65535, 65536, 131070, 131071]
+    O = admm.solve_request(r.samples[pick], r.H, r.dt, r.bounds, r.q0, r.v0, iters=40,
+                           alpha=1.8, weights=P.weights)
+    err = np.abs(out.cpu().numpy()[pick] - O.x).max()
+    print(f"131072 samples x 12 joints: max-abs {err:.3e}")
+    assert err <= 1e-4
+    np.testing.assert_allclose(rp.cpu().numpy()[pick], O.r_p, atol=1e-4, rtol=1e-3)
+    P.close()
