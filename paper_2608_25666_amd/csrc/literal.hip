@@ -27,6 +27,8 @@
 // P = I + 2 delta C^T W C (the projection's factor with rho = 2 delta and block
 // weights W). C^T W c is nonzero only at steps 1 and 2 (1-based); step 1 of
 // rhs is absorbed by the equality multiplier, leaving -2 delta W_J v0 at step 2.
+// K's column of step 1 is zero (the step is pinned), so it carries k instead and
+// rhs_1 is set to v0: x' = K rhs + k v0 is one product.
 // Step 3 is then w' = w + (delta/2) u - delta C^T W s(x'); since x' solves
 // P x' + e_1 mu = rhs, delta C^T W C x' = (rhs - x' - e_1 mu) / 2, and Step 3
 // reduces exactly to w' = (w + x') / 2 on steps 2..H, which the kernel uses.
