@@ -111,7 +111,7 @@ struct TileSolver {
   float qv[HQ], qq[HQ], qa[HQ], qj[HQ];
   float sw[HQ];
   float se[HQ];
-  float offw, offe;
+  float sfw[3], sfe[3];   // higher chunks' transposed position sums (raw reads)
   float rpm, rdm;
 
   int lane, g, nvalid;
@@ -143,13 +143,17 @@ struct TileSolver {
     c = (g < 3) ? 0.0f : c;
     return a + (b + c);
   }
-  __device__ __forceinline__ float excl_suffix(float T) const {   // sum over higher chunks
-    float a = lane_read(T, a_next);    // chunk g+1
-    float b = lane_read(T, a_next2);   // chunk g+2
-    float c = lane_read(T, a_prev);    // chunk g+3 (lane + 48 = lane - 16 mod 64)
-    a = (g == 3) ? 0.0f : a;
-    b = (g >= 2) ? 0.0f : b;
-    c = (g >= 1) ? 0.0f : c;
+  // Sum over the higher chunks in two parts: the reads are issued where T is known
+  // and summed where the result is needed, so the LDS round trip overlaps other rows.
+  __device__ __forceinline__ void suffix_reads(float T, float (&r)[3]) const {
+    r[0] = lane_read(T, a_next);    // chunk g+1
+    r[1] = lane_read(T, a_next2);   // chunk g+2
+    r[2] = lane_read(T, a_prev);    // chunk g+3 (lane + 48 = lane - 16 mod 64)
+  }
+  __device__ __forceinline__ float suffix_sum(const float (&r)[3]) const {
+    const float a = (g == 3) ? 0.0f : r[0];
+    const float b = (g >= 2) ? 0.0f : r[1];
+    const float c = (g >= 1) ? 0.0f : r[2];
     return a + (b + c);
   }
 
@@ -177,6 +181,9 @@ struct TileSolver {
       (void)blk;
       if constexpr (CHECK) rpm = fmaxf(rpm, fabsf(ev));
     };
+    // the acceleration/jerk block's boundary values depend only on x: read them first
+    const float xprev_r = lane_read(X(HQ - 1), a_prev);
+    const float aprev_r = lane_read(X(HQ - 1) - X(HQ - 2), a_prev);
     // ---- position block: s = prefix sum (chunk prefix + lower chunks' totals)
     {
       float acc = 0.0f;
@@ -199,8 +206,8 @@ struct TileSolver {
         sw[i] = suf;
         if constexpr (CHECK) { sufe = fmaf(cQ, se[i], sufe); se[i] = sufe; }
       }
-      offw = excl_suffix(suf);
-      if constexpr (CHECK) offe = excl_suffix(sufe);
+      suffix_reads(suf, sfw);
+      if constexpr (CHECK) suffix_reads(sufe, sfe);
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- velocity block: s = x
@@ -215,14 +222,13 @@ struct TileSolver {
     // C_A^T w_A + cJ C_J^T w_J = D^T v with v_k = wA_k + cJ (wJ_k - wJ_{k+1}),
     // (D^T v)_k = v_k - v_{k+1}.
     {
-      const float xl = X(HQ - 1);
-      const float al = X(HQ - 1) - X(HQ - 2);
-      float xprev = lane_read(xl, a_prev);
-      float aprev = lane_read(al, a_prev);
-      xprev = (g == 0) ? v0 : xprev;
-      aprev = (g == 0) ? 0.0f : aprev;
+      float xprev = (g == 0) ? v0 : xprev_r;
+      float aprev = (g == 0) ? 0.0f : aprev_r;
       float wa_p = 0.0f, wj_p = 0.0f, wj_0 = 0.0f, v_0 = 0.0f, v_pm = 0.0f;
       float ea_p = 0.0f, ej_p = 0.0f, ej_0 = 0.0f, ve_0 = 0.0f, ve_pm = 0.0f;
+      // the next chunk's first terms are read as soon as they exist (step 2 of the
+      // chunk) and used after the loop
+      float wj_nr = 0.0f, v_nr = 0.0f, ej_nr = 0.0f, ve_nr = 0.0f;
 #pragma unroll
       for (int i = 0; i < HQ; ++i) {
         const float sa = X(i) - xprev;
@@ -247,7 +253,13 @@ struct TileSolver {
           if constexpr (CHECK) ve = fmaf(cJ, ej_p - ej, ea_p);
           if (i == 1) {
             v_0 = v;
-            if constexpr (CHECK) ve_0 = ve;
+            wj_nr = lane_read(wj_0, a_next);
+            v_nr = lane_read(v_0, a_next);
+            if constexpr (CHECK) {
+              ve_0 = ve;
+              ej_nr = lane_read(ej_0, a_next);
+              ve_nr = lane_read(ve_0, a_next);
+            }
           } else {
             sw[i - 2] += v_pm - v;
             if constexpr (CHECK) se[i - 2] += ve_pm - ve;
@@ -259,26 +271,25 @@ struct TileSolver {
         wj_p = wj;
         if constexpr (CHECK) { ea_p = ea; ej_p = ej; }
       }
-      float wj_n = lane_read(wj_0, a_next);
-      wj_n = (g == 3) ? 0.0f : wj_n;
+      const float wj_n = (g == 3) ? 0.0f : wj_nr;
       const float v_last = fmaf(cJ, wj_p - wj_n, wa_p);
       sw[HQ - 2] += v_pm - v_last;
-      float v_n = lane_read(v_0, a_next);
-      v_n = (g == 3) ? 0.0f : v_n;
+      const float v_n = (g == 3) ? 0.0f : v_nr;
       sw[HQ - 1] += v_last - v_n;
       if constexpr (CHECK) {
-        float ej_n = lane_read(ej_0, a_next);
-        ej_n = (g == 3) ? 0.0f : ej_n;
+        const float ej_n = (g == 3) ? 0.0f : ej_nr;
         const float ve_last = fmaf(cJ, ej_p - ej_n, ea_p);
         se[HQ - 2] += ve_pm - ve_last;
-        float ve_n = lane_read(ve_0, a_next);
-        ve_n = (g == 3) ? 0.0f : ve_n;
+        const float ve_n = (g == 3) ? 0.0f : ve_nr;
         se[HQ - 1] += ve_last - ve_n;
       }
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- defect d = (x~ - x) + rho C^T w; dual residual on check iterations
     if constexpr (CHECK) rdm = 0.0f;
+    const float offw = suffix_sum(sfw);
+    float offe = 0.0f;
+    if constexpr (CHECK) offe = suffix_sum(sfe);
 #pragma unroll
     for (int i = 0; i < HQ; ++i) {
       const float d = fmaf(rho, sw[i] + offw, xt_lds[i * 64 + lane] - X(i));
