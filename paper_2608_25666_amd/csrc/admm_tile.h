@@ -304,25 +304,32 @@ struct TileSolver {
   }
 
   // x += K d with FP32 operands (v_mfma_f32_16x16x4_f32). Fragments stream
-  // from LDS one float4 ahead; the barriers keep the scheduler from hoisting
+  // from LDS ahead of use; the barriers keep the scheduler from hoisting
   // the whole of K into registers.
   __device__ __forceinline__ void gemm_f32(const float* __restrict__ kf) {
     __asm__ volatile("" ::: "memory");
     const v4f* k4 = reinterpret_cast<const v4f*>(kf) + lane;
-    v4f a = k4[0];
+    // two fragments in flight (one for chunks above 24, where the registers are
+    // spoken for): a block's last group can hold a single MFMA, too little cover
+    // for one LDS round trip. Slots rotate by group index (compile-time after
+    // unrolling), so no register moves.
+    constexpr int total = NB * NJ4;
+    constexpr int ahead = HQ <= 24 ? 2 : 1;
+    v4f f[ahead + 1];
+    f[0] = k4[0];
+    if (ahead == 2 && total > 1) f[1] = k4[64];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
       for (int jj = 0; jj < NJ4; ++jj) {
         const int idx = b * NJ4 + jj;
-        v4f an = a;
-        if (idx + 1 < NB * NJ4) an = k4[(idx + 1) * 64];
+        if (idx + ahead < total) f[(idx + ahead) % (ahead + 1)] = k4[(idx + ahead) * 64];
+        const v4f a = f[idx % (ahead + 1)];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int j = 4 * jj + e;
           if (j < HQ) xb[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], sw[j], xb[b], 0, 0, 0);
         }
-        a = an;
         __builtin_amdgcn_sched_barrier(0);
       }
     }
