@@ -112,6 +112,8 @@ struct TileSolver {
   float sw[HQ];
   float se[HQ];
   float sfw[3], sfe[3];   // higher chunks' transposed position sums (raw reads)
+  static constexpr int kXtAhead = HQ <= 13 ? HQ : 4;
+  float xt_ahead[kXtAhead];   // first samples of the chunk, read ahead of the defect stage
   float rpm, rdm;
 
   int lane, g, nvalid;
@@ -222,6 +224,10 @@ struct TileSolver {
     // C_A^T w_A + cJ C_J^T w_J = D^T v with v_k = wA_k + cJ (wJ_k - wJ_{k+1}),
     // (D^T v)_k = v_k - v_{k+1}.
     {
+      // the defect stage's first samples come from LDS while these rows run
+#pragma unroll
+      for (int i = 0; i < kXtAhead; ++i) xt_ahead[i] = xt_lds[i * 64 + lane];
+      __builtin_amdgcn_sched_barrier(0);   // keep the reads here, ahead of the rows
       float xprev = (g == 0) ? v0 : xprev_r;
       float aprev = (g == 0) ? 0.0f : aprev_r;
       float wa_p = 0.0f, wj_p = 0.0f, wj_0 = 0.0f, v_0 = 0.0f, v_pm = 0.0f;
@@ -292,7 +298,8 @@ struct TileSolver {
     if constexpr (CHECK) offe = suffix_sum(sfe);
 #pragma unroll
     for (int i = 0; i < HQ; ++i) {
-      const float d = fmaf(rho, sw[i] + offw, xt_lds[i * 64 + lane] - X(i));
+      const float xt = i < kXtAhead ? xt_ahead[i] : xt_lds[i * 64 + lane];
+      const float d = fmaf(rho, sw[i] + offw, xt - X(i));
       sw[i] = d;
       if constexpr (CHECK) {
         float r = fabsf(fmaf(rho, se[i] + offe, -d));
