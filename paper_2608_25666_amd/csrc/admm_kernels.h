@@ -18,7 +18,8 @@
 namespace prism {
 
 // Chunk sizes up to this one fit in 256 registers per lane, so two waves share
-// each SIMD and one wave's MFMA work overlaps the other's VALU work.
+// each SIMD and each covers the other's dependency waits (the SIMD does not run
+// one wave's VALU work beside the other's MFMA work).
 constexpr int kMaxHQTwoWaves = 16;
 
 template <int HQ, bool EXACT, int GEMM, bool PLAN = false>
@@ -106,10 +107,25 @@ SolveKernelFn kernel_for() {
 }
 
 // Optimizer-step variant: samples drawn in the load, tracking cost in the
-// epilogue (one wave per SIMD; used by prism_plan_step).
+// epilogue (used by prism_plan_step). The sampling and cost code need registers of
+// their own: two waves per SIMD fit without spills up to chunk 13 with the FP32
+// x-update and chunk 12 with the 16-bit ones.
+constexpr int max_hq_two_waves_plan(int gemm) { return gemm == GEMM_F32 ? 13 : 12; }
+template <int HQ, int GEMM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void
+admm_plan_kernel_2w(SolveKernelArgs A) {
+  solve_body<HQ, false, GEMM, true>(A);
+}
+
 template <int HQ, int GEMM>
 __global__ __launch_bounds__(256) void admm_plan_kernel(SolveKernelArgs A) {
   solve_body<HQ, false, GEMM, true>(A);
+}
+
+template <int HQ, int GEMM>
+SolveKernelFn plan_kernel_for() {
+  if constexpr (HQ <= max_hq_two_waves_plan(GEMM)) return admm_plan_kernel_2w<HQ, GEMM>;
+  else return admm_plan_kernel<HQ, GEMM>;
 }
 
 SolveKernelFn plan_kernel_f32(int HQ);

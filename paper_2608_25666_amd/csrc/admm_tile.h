@@ -112,7 +112,7 @@ struct TileSolver {
   float sw[HQ];
   float se[HQ];
   float sfw[3], sfe[3];   // higher chunks' transposed position sums (raw reads)
-  static constexpr int kXtAhead = HQ <= 13 ? HQ : 4;
+  static constexpr int kXtAhead = HQ <= 13 ? (PLAN ? (HQ < 4 ? HQ : 4) : HQ) : (HQ <= 24 ? 4 : 1);
   float xt_ahead[kXtAhead];   // first samples of the chunk, read ahead of the defect stage
   float rpm, rdm;
 
