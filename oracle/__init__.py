@@ -15,7 +15,7 @@ Contents (each function cites the passage of the paper it follows):
                      factorization, and the reduced inverse (K, k);
 * ``admm``        -- the headline ADMM iteration (scaled dual, velocity-unit
                      rows), the paper's printed Bregman iteration as a flag,
-                     residuals, grouped early exit and warm start;
+                     residuals, per-column early exit and warm start;
 * ``exact``       -- independent exact-projection checkers: brute-force face
                      enumeration for tiny horizons, active-set polishing, and a
                      KKT certificate with non-negative least squares;

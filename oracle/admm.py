@@ -41,10 +41,14 @@ Residuals (per column, velocity units, rad/s):
 The stationarity row k = 1 is excluded because the equality multiplier mu of
 x_1 = v0 absorbs it.
 
-Early exit. Columns are grouped 16 samples of one joint at a time (samples
-16g .. 16g+15). With a tolerance, a group stops at the first check point
-(iteration 0, every ``check_every`` iterations, and ``max_iters``) where every
-column in it has max(r_p, r_d) <= tol.
+Early exit. With a tolerance, each column stops at the first check point
+(iteration 0, every ``check_every`` iterations, and its cap) where its own
+max(r_p, r_d) <= tol. The paper gives no stopping rule (Sec. III-D
+"Convergence" speaks only of low residuals), so the plain reading is per
+column; how a solver groups columns for stopping is its own business and is
+checked against this per-column definition, not built into it. ``iters`` may
+also be an array with one count per column: column c then runs exactly
+iters[c] iterations (or stops earlier at the tolerance).
 
 Block penalties. The paper's penalty delta is one scalar. A positive diagonal
 penalty R = rho * diag(w_V, w_Q, w_A, w_J) (one weight per constraint block)
@@ -70,7 +74,6 @@ import numpy as np
 from . import problem
 from .factor import KKTFactor, penalty_matrix
 
-GROUP = 16
 
 
 @dataclasses.dataclass
@@ -98,24 +101,16 @@ def block_penalty(H: int, rho: float, weights=None) -> np.ndarray:
                                  np.full(H - 1, w[3])])
 
 
-def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
-               q0: float, v0: float, rho: float = 1.0, alpha: float = 1.0,
-               iters: int = 100, tol: Optional[float] = None, check_every: int = 10,
-               group: int = GROUP, warm_x: Optional[np.ndarray] = None,
-               warm_y: Optional[np.ndarray] = None, weights=None,
-               warm_z: Optional[np.ndarray] = None) -> JointResult:
-    """Headline ADMM for the columns of one joint.
+def start_state(xt: np.ndarray, C: np.ndarray, lo: np.ndarray, hi: np.ndarray,
+                R: np.ndarray, v0: float, alpha: float, warm_x=None, warm_y=None,
+                warm_z=None):
+    """Starting point and the first slack/multiplier pass (reading R3).
 
-    xt_cols: (ncols, H) samples x~. With ``tol`` None the iteration runs exactly
-    ``iters`` times; otherwise ``iters`` is the cap and groups stop early.
-    ``weights``: block penalty weights (w_V, w_Q, w_A, w_J), default all 1.
+    xt: (H, ncols) samples; lo, hi, R: (rows, 1). Returns (x0, z0, y0), all
+    (rows or H, ncols): x0 = x~ (or the warm iterate) with x0_1 := v0, s0 = C x0,
+    s^0 = alpha s0 + (1 - alpha) z_w (z_w = s0 when absent),
+    z0 = clip(s^0 + R^-1 y_w), y0 = y_w + R (s^0 - z0).
     """
-    rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
-    C, lo, hi = rows.C, rows.lo[:, None], rows.hi[:, None]
-    Rv = block_penalty(H, rho, weights)
-    R = Rv[:, None]
-    fac = KKTFactor(np.eye(H) + C.T @ (R * C))
-    xt = np.asarray(xt_cols, dtype=np.float64).T.copy()         # (H, ncols)
     ncols = xt.shape[1]
     x = (xt.copy() if warm_x is None else np.asarray(warm_x, dtype=np.float64).T.copy())
     x[0, :] = v0
@@ -126,39 +121,73 @@ def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
     shat0 = alpha * s0 + (1.0 - alpha) * zw
     z = np.clip(shat0 + y / R, lo, hi)
     y = y + R * (shat0 - z)
+    return x, z, y
+
+
+def relaxed_step(xt: np.ndarray, z: np.ndarray, y: np.ndarray, C: np.ndarray, lo: np.ndarray,
+                 hi: np.ndarray, R: np.ndarray, fac: KKTFactor, v0: float, alpha: float):
+    """One ADMM iteration on the paper's splitting, multiplier in constraint space.
+
+    Step 2 (eqs. (admm_primal), (admm_KKT)): x+ solves
+        M [x; mu] = [x~ + C^T (R z - y); v0],  P = I + C^T R C,
+    i.e. x+ minimises 1/2||x - x~||^2 + 1/2||C x - z + R^-1 y||_R^2 with x_1 = v0.
+    Relaxation: s^ = alpha C x+ + (1 - alpha) z (alpha = 1: none).
+    Step 1 (eq. (admm_zeta), slack projection): z+ = clip(s^ + R^-1 y, lo, hi).
+    Step 3 (eq. (admm_dual), multiplier step): y+ = y + R (s^ - z+).
+    Arrays are (rows or H, ncols); lo, hi, R are (rows, 1). Returns (x+, z+, y+).
+    """
+    r = xt + C.T @ (R * z - y)
+    x_new = fac.solve(r, v0)
+    shat = alpha * (C @ x_new) + (1.0 - alpha) * z
+    z_new = np.clip(shat + y / R, lo, hi)
+    y_new = y + R * (shat - z_new)
+    return x_new, z_new, y_new
+
+
+def admm_joint(xt_cols: np.ndarray, H: int, dt: float, lim: problem.JointLimits,
+               q0: float, v0: float, rho: float = 1.0, alpha: float = 1.0,
+               iters=100, tol: Optional[float] = None, check_every: int = 10,
+               warm_x: Optional[np.ndarray] = None,
+               warm_y: Optional[np.ndarray] = None, weights=None,
+               warm_z: Optional[np.ndarray] = None) -> JointResult:
+    """Headline ADMM for the columns of one joint.
+
+    xt_cols: (ncols, H) samples x~. ``iters``: one count for every column or an
+    array of per-column counts. With ``tol`` None each column runs exactly its
+    count; otherwise the count is its cap and the column stops at the first
+    check point where its own max(r_p, r_d) <= tol.
+    ``weights``: block penalty weights (w_V, w_Q, w_A, w_J), default all 1.
+    """
+    rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
+    C, lo, hi = rows.C, rows.lo[:, None], rows.hi[:, None]
+    R = block_penalty(H, rho, weights)[:, None]
+    fac = KKTFactor(np.eye(H) + C.T @ (R * C))
+    xt = np.asarray(xt_cols, dtype=np.float64).T.copy()         # (H, ncols)
+    ncols = xt.shape[1]
+    cap = np.broadcast_to(np.asarray(iters, dtype=np.int64), (ncols,)).copy()
+    if np.any(cap < 0):
+        raise ValueError("iteration counts must be >= 0")
+    x, z, y = start_state(xt, C, lo, hi, R, v0, alpha, warm_x, warm_y, warm_z)
 
     done = np.zeros(ncols, dtype=bool)
-    n_done = np.full(ncols, iters, dtype=np.int64)
-    gid = np.arange(ncols) // group
-    n_groups = int(gid.max()) + 1 if ncols else 0
+    n_done = cap.copy()
 
-    def check(l):
+    def check(l, cols):
         if tol is None:
             return
         r_p, r_d = residuals(C, x, xt, z, y)
-        ok = np.maximum(r_p, r_d) <= tol
-        for g in range(n_groups):
-            m = gid == g
-            if not done[m].any() and ok[m].all():
-                done[m] = True
-                n_done[m] = l
+        hit = cols & ~done & (np.maximum(r_p, r_d) <= tol)
+        done[hit] = True
+        n_done[hit] = l
 
-    check(0)
-    for l in range(1, iters + 1):
-        if done.all():
+    check(0, np.ones(ncols, dtype=bool))
+    for l in range(1, int(cap.max(initial=0)) + 1):
+        act = ~done & (l <= cap)
+        if not act.any():
             break
-        act = ~done
-        xa, za, ya = x[:, act], z[:, act], y[:, act]
-        r = xt[:, act] + C.T @ (R * za - ya)
-        x_new = fac.solve(r, v0)
-        s = C @ x_new
-        shat = alpha * s + (1.0 - alpha) * za
-        z_new = np.clip(shat + ya / R, lo, hi)
-        y_new = ya + R * (shat - z_new)
-        x[:, act], z[:, act], y[:, act] = x_new, z_new, y_new
-        del xa
-        if l % check_every == 0 or l == iters:
-            check(l)
+        x[:, act], z[:, act], y[:, act] = relaxed_step(xt[:, act], z[:, act], y[:, act], C, lo,
+                                                       hi, R, fac, v0, alpha)
+        check(l, act & ((l % check_every == 0) | (l == cap)))
     r_p, r_d = residuals(C, x, xt, z, y)
     return JointResult(x=x.T.copy(), r_p=r_p, r_d=r_d, iters=n_done, z=z.T.copy(), y=y.T.copy())
 
@@ -174,15 +203,22 @@ class RequestResult:
 
 
 def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
-                  rho: float = 1.0, alpha: float = 1.0, iters: int = 100,
+                  rho: float = 1.0, alpha: float = 1.0, iters=100,
                   tol: Optional[float] = None, check_every: int = 10,
                   warm_x: Optional[np.ndarray] = None,
                   warm_y: Optional[np.ndarray] = None, weights=None,
                   warm_z: Optional[np.ndarray] = None) -> RequestResult:
-    """Project every sample of a request (layout [N][H][nj]), joint by joint."""
+    """Project every sample of a request (layout [N][H][nj]), joint by joint.
+
+    ``iters``: one count (or cap) for all columns, or an [N][nj] array of
+    per-column counts."""
     samples = np.asarray(samples)
     N, H_, nj = samples.shape
     assert H_ == H
+    iters = np.asarray(iters, dtype=np.int64)
+    per_col = iters.ndim > 0
+    if per_col:
+        iters = np.broadcast_to(iters, (N, nj))
     x = np.zeros((N, H, nj))
     r_p = np.zeros((N, nj))
     r_d = np.zeros((N, nj))
@@ -192,7 +228,8 @@ def solve_request(samples: np.ndarray, H: int, dt: float, bounds, q0, v0,
     for j in range(nj):
         lim = problem.joint_limits(bounds, j)
         res = admm_joint(samples[:, :, j], H, dt, lim, float(q0[j]), float(v0[j]), rho=rho,
-                         alpha=alpha, iters=iters, tol=tol, check_every=check_every,
+                         alpha=alpha, iters=iters[:, j] if per_col else int(iters), tol=tol,
+                         check_every=check_every,
                          warm_x=None if warm_x is None else warm_x[:, :, j],
                          warm_y=None if warm_y is None else warm_y[:, j, :],
                          weights=weights,

@@ -189,22 +189,42 @@ def test_joint_separability_against_stacked_problem():
         assert np.max(np.abs(B @ w - (xt - x))) < 1e-7
 
 
-def test_grouped_early_exit():
+def test_per_column_early_exit():
+    """Each column stops at the first check point where its own max(r_p, r_d) <= tol:
+    its count is a check point, the residual meets tol there, and a fixed-count run one
+    check period shorter leaves that column above tol. A run with per-column counts
+    equal to the stops reproduces the early-exit iterates bit for bit."""
     r = W.white_batch()
+    tol, ce = 1e-3, 10
     res = admm.solve_request(r.samples[:40], r.H, r.dt, r.bounds, r.q0, r.v0, iters=5000,
-                             tol=1e-3, check_every=10)
-    assert np.all(res.iters % 10 == 0)
-    assert np.all(np.maximum(res.r_p, res.r_d) <= 1e-3)
-    # groups are samples 0-15, 16-31, 32-39 of each joint: one stop count per group
-    for j in range(r.nj):
-        for g0, g1 in ((0, 16), (16, 32), (32, 40)):
-            assert len(set(res.iters[g0:g1, j].tolist())) == 1
-    # fixed-count run with the same count reproduces the early-exit result exactly
-    j = 5
-    n = int(res.iters[0, j])
-    lim = problem.joint_limits(r.bounds, j)
-    fixed = admm.admm_joint(r.samples[:16, :, j], r.H, r.dt, lim, r.q0[j], r.v0[j], iters=n)
-    np.testing.assert_array_equal(fixed.x, res.x[:16, :, j])
+                             tol=tol, check_every=ce)
+    assert np.all(res.iters % ce == 0)
+    assert np.all(np.maximum(res.r_p, res.r_d) <= tol)
+    assert len(np.unique(res.iters)) > 5          # columns of one joint stop apart
+    fixed = admm.solve_request(r.samples[:40], r.H, r.dt, r.bounds, r.q0, r.v0,
+                               iters=res.iters)
+    np.testing.assert_array_equal(fixed.x, res.x)
+    np.testing.assert_array_equal(fixed.iters, res.iters)
+    before = admm.solve_request(r.samples[:40], r.H, r.dt, r.bounds, r.q0, r.v0,
+                                iters=np.maximum(res.iters - ce, 0))
+    late = np.maximum(before.r_p, before.r_d)
+    assert np.all(late[res.iters > 0] > tol)
+
+
+def test_per_column_counts_equal_separate_runs():
+    """Column c of a run with counts iters[c] equals a run of that column alone (to BLAS
+    rounding, which depends on how many columns share a product)."""
+    r = W.make_request(8, N=5, H=12, nj=1, dt=0.05, kind="white", sigma=1.5)
+    lim = problem.joint_limits(r.bounds, 0)
+    counts = np.array([0, 1, 7, 30, 12])
+    kw = dict(alpha=1.8, weights=(1.7, 2.125 / 12, 13.6, 17.0))
+    a = admm.admm_joint(r.samples[:, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0], iters=counts, **kw)
+    for c, n in enumerate(counts):
+        b = admm.admm_joint(r.samples[c:c + 1, :, 0], r.H, r.dt, lim, r.q0[0], r.v0[0],
+                            iters=int(n), **kw)
+        np.testing.assert_allclose(a.x[c], b.x[0], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(a.y[c], b.y[0], rtol=0, atol=1e-11)
+    assert np.all(a.iters == counts)
 
 
 def test_warm_start_at_solution_is_fixed_point():
@@ -435,3 +455,170 @@ def test_literal_feasible_sample_is_a_fixed_point():
     x, viol = admm.literal_joint(xt, H, dt, lim, q0, v0, delta=1.0, iters=50)
     np.testing.assert_allclose(x, xt, atol=1e-12)
     assert np.all(viol == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# The over-relaxed step (alpha != 1) as the benchmarks run it
+# ---------------------------------------------------------------------------
+
+ALPHA = 1.8
+
+
+def _default_weights(H):
+    return (1.7, 2.125 / H, 13.6, 17.0)
+
+
+def _row_penalty(H, rho, w):
+    """R written out per row: velocity, position, acceleration rows (H each), jerk (H-1)."""
+    return np.concatenate([np.full(H, rho * w[0]), np.full(H, rho * w[1]),
+                           np.full(H, rho * w[2]), np.full(H - 1, rho * w[3])])
+
+
+def _single_state_iterates(xt, C, lo, hi, Rv, v0, alpha, counts):
+    """The iteration in its single-state form, written independently of the oracle and in
+    dense FP64: one state per constraint row, q = (1 - alpha) z + R^-1 y, and an
+    incremental primal step through the inverse of the bordered KKT matrix
+    [[I + C^T R C, e1], [e1^T, 0]]:
+        t = alpha C x + q,  z = clip(t),  q' = t - alpha z,
+        d = (x~ - x) + C^T R (2 z - t - C x),  x' = x + K d.
+    Cold start q = (1 - alpha) C x0 with x0 = x~, x0_1 := v0. Returns {L: (x_L, q_L)}
+    for every L in counts (x: (ncols, H), q: (ncols, rows))."""
+    H = C.shape[1]
+    M = np.zeros((H + 1, H + 1))
+    M[:H, :H] = np.eye(H) + C.T @ (Rv[:, None] * C)
+    M[0, H] = M[H, 0] = 1.0
+    K = np.linalg.inv(M)[:H, :H]
+    x = np.array(xt, dtype=np.float64)
+    x[:, 0] = v0
+    q = (1.0 - alpha) * (x @ C.T)
+    out = {}
+    for L in range(max(counts) + 1):
+        s = x @ C.T
+        t = alpha * s + q
+        z = np.clip(t, lo, hi)
+        q = t - alpha * z
+        if L in counts:
+            out[L] = (x.copy(), q.copy())
+        d = (xt - x) + ((2.0 * z - t - s) * Rv) @ C
+        x = x + d @ K.T
+    return out
+
+
+def _relaxed_step_violations(alpha=ALPHA, H=20, dt=0.05, rho=1.0, seed=44):
+    """Largest violation of each defining property of one relaxed step, taken after
+    L iterations (z != C x and y != 0 by then):
+      grad   x+ minimises 1/2||x - x~||^2 + 1/2||C x - z + R^-1 y||_R^2 with x_1 = v0
+             (zero gradient on steps 2..H, x+_1 = v0);
+      box    z+ inside [lo, hi];
+      cone   y+ in the normal cone of the box at z+ (0 inside, >= 0 at hi, <= 0 at lo);
+      prox   z+ + R^-1 y+ = s^ + R^-1 y with s^ = alpha C x+ + (1 - alpha) z, so that
+             (box, cone, prox) make z+ the projection of s^ + R^-1 y onto the box;
+      chain  x after L = 1, 2, 5, 30 iterations equals the single-state recurrence."""
+    rng = np.random.default_rng(seed)
+    lim = _lim()
+    q0, v0 = 0.05, 0.4
+    w = _default_weights(H)
+    rows = problem.velocity_unit_rows(H, dt, lim, q0, v0)
+    C, lo, hi = rows.C, rows.lo, rows.hi
+    Rv = _row_penalty(H, rho, w)
+    xt = rng.normal(0, 2, (4, H))
+    kw = dict(rho=rho, alpha=alpha, weights=w)
+    v = {}
+    for L in (3, 11):
+        a = admm.admm_joint(xt, H, dt, lim, q0, v0, iters=L, **kw)
+        b = admm.admm_joint(xt, H, dt, lim, q0, v0, iters=L + 1, **kw)
+        x1, z0, y0, z1, y1 = b.x, a.z, a.y, b.z, b.y
+        grad = (x1 - xt) + ((x1 @ C.T - z0) * Rv + y0) @ C
+        v["grad"] = max(v.get("grad", 0.0), np.abs(grad[:, 1:]).max(), np.abs(x1[:, 0] - v0).max())
+        v["box"] = max(v.get("box", 0.0), np.maximum(lo - z1, 0).max(), np.maximum(z1 - hi, 0).max())
+        inside = (z1 > lo + 1e-9) & (z1 < hi - 1e-9)
+        at_hi = np.isclose(z1, hi, rtol=0, atol=1e-9)
+        at_lo = np.isclose(z1, lo, rtol=0, atol=1e-9)
+        cone = np.concatenate([np.abs(y1[inside]), np.maximum(-y1[at_hi & ~at_lo], 0),
+                               np.maximum(y1[at_lo & ~at_hi], 0), [0.0]])
+        v["cone"] = max(v.get("cone", 0.0), cone.max())
+        shat = alpha * (x1 @ C.T) + (1.0 - alpha) * z0
+        v["prox"] = max(v.get("prox", 0.0), np.abs(z1 + y1 / Rv - (shat + y0 / Rv)).max())
+    counts = (1, 2, 5, 30)
+    ref = _single_state_iterates(xt, C, lo, hi, Rv, v0, alpha, counts)
+    chain = 0.0
+    for L in counts:
+        o = admm.admm_joint(xt, H, dt, lim, q0, v0, iters=L, **kw)
+        chain = max(chain, np.abs(o.x - ref[L][0]).max())
+        q = (1.0 - alpha) * o.z + o.y / Rv
+        chain = max(chain, np.abs(q - ref[L][1]).max())
+    v["chain"] = chain
+    return v
+
+
+@pytest.mark.parametrize("alpha", [ALPHA, 1.0, 1.5])
+def test_relaxed_step_defining_properties(alpha):
+    """alpha = 1.8 (the benchmarks'), the default block weights: each step satisfies the
+    optimality conditions of its two subproblems and the iterates equal an independently
+    written single-state recurrence."""
+    v = _relaxed_step_violations(alpha=alpha)
+    print({k: f"{x:.1e}" for k, x in v.items()})
+    for k, x in v.items():
+        assert x <= 1e-9, (k, x)
+
+
+def _mut_y_from_s(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: the multiplier step uses s = C x+ instead of the relaxed s^."""
+    x = fac.solve(xt + C.T @ (R * z - y), v0)
+    s = C @ x
+    shat = alpha * s + (1.0 - alpha) * z
+    zn = np.clip(shat + y / R, lo, hi)
+    return x, zn, y + R * (s - zn)
+
+
+def _mut_z_from_s(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: the slack step projects s + R^-1 y instead of s^ + R^-1 y."""
+    x = fac.solve(xt + C.T @ (R * z - y), v0)
+    s = C @ x
+    shat = alpha * s + (1.0 - alpha) * z
+    zn = np.clip(s + y / R, lo, hi)
+    return x, zn, y + R * (shat - zn)
+
+
+def _mut_no_relaxation(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: alpha ignored (s^ = s in both steps)."""
+    x = fac.solve(xt + C.T @ (R * z - y), v0)
+    s = C @ x
+    zn = np.clip(s + y / R, lo, hi)
+    return x, zn, y + R * (s - zn)
+
+
+def _mut_relaxation_sign(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: s^ = alpha s - (1 - alpha) z."""
+    x = fac.solve(xt + C.T @ (R * z - y), v0)
+    shat = alpha * (C @ x) - (1.0 - alpha) * z
+    zn = np.clip(shat + y / R, lo, hi)
+    return x, zn, y + R * (shat - zn)
+
+
+def _mut_unscaled_multiplier(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: the slack step adds y instead of R^-1 y."""
+    x = fac.solve(xt + C.T @ (R * z - y), v0)
+    shat = alpha * (C @ x) + (1.0 - alpha) * z
+    zn = np.clip(shat + y, lo, hi)
+    return x, zn, y + R * (shat - zn)
+
+
+def _mut_relaxed_primal_rhs(xt, z, y, C, lo, hi, R, fac, v0, alpha):
+    """Planted mistake: the primal right-hand side uses C^T (R z + y)."""
+    x = fac.solve(xt + C.T @ (R * z + y), v0)
+    shat = alpha * (C @ x) + (1.0 - alpha) * z
+    zn = np.clip(shat + y / R, lo, hi)
+    return x, zn, y + R * (shat - zn)
+
+
+@pytest.mark.parametrize("mutant", [_mut_y_from_s, _mut_z_from_s, _mut_no_relaxation,
+                                    _mut_relaxation_sign, _mut_unscaled_multiplier,
+                                    _mut_relaxed_primal_rhs])
+def test_relaxed_step_pins_reject_planted_mistakes(monkeypatch, mutant):
+    """Each plausible mistake in the oracle's relaxed step, planted in the oracle, breaks
+    at least one pin of test_relaxed_step_defining_properties at alpha = 1.8."""
+    monkeypatch.setattr(admm, "relaxed_step", mutant)
+    v = _relaxed_step_violations(alpha=ALPHA)
+    print(mutant.__name__, {k: f"{x:.1e}" for k, x in v.items()})
+    assert max(v.values()) > 1e-3
