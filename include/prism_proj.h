@@ -85,8 +85,10 @@ typedef struct {
   int32_t fp32_tail;    /* reduced forms: with tol <= 0 the last fp32_tail of the
                            iterations use the FP32 GEMM. With tol > 0 the reduced
                            GEMM runs until a group meets tol; then (if fp32_tail >
-                           0) fp32_tail FP32 iterations follow and the group stops
-                           at the next check that meets tol, staying in FP32       */
+                           0) exactly fp32_tail FP32 iterations follow (check points
+                           inside them do not stop the group), and the group stops
+                           at their end if it meets tol there, else at the first
+                           later check point that does, staying in FP32           */
   float alpha;          /* over-relaxation in (0, 2); 1 = plain ADMM                 */
   float tol;            /* <= 0: run exactly `iters` iterations. > 0: each group of
                            16 samples of one joint stops at the first check point
@@ -152,8 +154,14 @@ prism_status_t prism_proj_get_options(prism_proj_t p, prism_options_t* opts);
  *            |x_k - x~_k + (C^T y)_k| (rad/s), the stationarity gap.
  * Either residual pointer may be NULL.
  * Returns PRISM_EINFEASIBLE when v0 is outside [v_min, v_max], q0 + dt*v0
- * is outside [q_min, q_max], or 0 is outside [a_min, a_max] or [j_min, j_max]
- * for some joint (the first rows would be unsatisfiable). N = 0 is a no-op. */
+ * is outside [q_min, q_max], or 0 is outside [a_min, a_max] for some joint (the
+ * rows of step 1 fixed by x_1 = v0 would be unsatisfiable; jerk rows start at
+ * step 2, eq. (jerk_stack), so the jerk bounds need not contain 0). N = 0 is a
+ * no-op. Any number of solves may be in flight on one handle, on any streams:
+ * a solve that takes over a tile-queue counter set from an earlier one waits on
+ * its own stream for that solve to finish (64 sets per handle; under graph
+ * capture this ordering is not recorded, so a captured graph must not be
+ * launched while an earlier launch of it is still running). */
 prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N,
                                 const double* q0, const double* v0, int iters, float* v_out,
                                 float* r_primal, float* r_dual, hipStream_t stream);

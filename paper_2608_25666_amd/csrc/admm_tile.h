@@ -119,6 +119,10 @@ struct TileSolver {
   int lane, g, nvalid;
   int a_prev, a_next, a_prev2, a_next2;   // ds_bpermute byte addresses
   float lbV, ubV, lbQ, ubQ, lbA, ubA, lbJ, ubJ, v0;
+  // bounds of the jerk row in chunk position 0: for chunk 0 that row (step 1) is
+  // outside the problem (jerk rows are steps 2..H) and identically zero, so its
+  // bounds are widened to hold 0 and the row stays inert (z = s = 0, q = 0)
+  float lbJ0, ubJ0;
   float rho, alpha, oma;
   float cV, cQ, cJ;   // block penalties relative to the acceleration block
 
@@ -243,7 +247,8 @@ struct TileSolver {
         aprev = sa;
         float ea = 0.0f, ej = 0.0f, ua = 0.0f, uj = 0.0f;
         float wa = mask(i, rowop<CHECK>(sa, qa[i], lbA, ubA, ea, ua));
-        float wj = mask(i, rowop<CHECK>(sj, qj[i], lbJ, ubJ, ej, uj));
+        float wj = mask(i, rowop<CHECK>(sj, qj[i], i == 0 ? lbJ0 : lbJ, i == 0 ? ubJ0 : ubJ,
+                                        ej, uj));
         if constexpr (CHECK) {
           ea = mask(i, ea);
           ej = mask(i, ej);
@@ -441,6 +446,8 @@ struct TileSolver {
     lbQ = jp.lb[1]; ubQ = jp.ub[1];
     lbA = jp.lb[2]; ubA = jp.ub[2];
     lbJ = jp.lb[3]; ubJ = jp.ub[3];
+    lbJ0 = (g == 0) ? fminf(lbJ, 0.0f) : lbJ;
+    ubJ0 = (g == 0) ? fmaxf(ubJ, 0.0f) : ubJ;
     v0 = jp.v0;
     rho = A.rho;
     alpha = A.alpha;
@@ -545,9 +552,10 @@ struct TileSolver {
     const int iters = A.iters;
     const int ce = A.check_every;
     // Fixed count: the last `tail` iterations run the FP32 GEMM. Residual-driven:
-    // the reduced GEMM runs until the group meets the tolerance, then `tail` FP32
-    // iterations follow and the group stops at the next check that still meets it
-    // (further FP32 iterations, checked every check_every, if it does not).
+    // the reduced GEMM runs until the tile meets the tolerance, then `tail` FP32
+    // iterations follow (check points inside the tail do not stop it) and the tile
+    // stops at the end of the tail if it still meets the tolerance there, else at the
+    // first later check point that does (FP32 iterations, checked every check_every).
     const int f32_from = !reduced ? 0 : (tolmode ? INT_MAX : iters - A.tail);
     bool f32p = !reduced;
     int it = 0;
@@ -560,9 +568,12 @@ struct TileSolver {
       if (tolmode) {
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
         if (wave_max(r) <= A.tol) {
-          if (f32p || A.tail <= 0) break;
-          f32p = true;
-          tail_end = it + A.tail;
+          // FP32 form (tail_end -1), or the FP32 tail has run: done
+          if (A.tail <= 0 || (f32p && it >= tail_end)) break;
+          if (!f32p) {
+            f32p = true;
+            tail_end = it + A.tail;
+          }
         } else if (it == tail_end) {
           tail_end = -1;
         }

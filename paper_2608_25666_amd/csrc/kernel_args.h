@@ -17,7 +17,8 @@ enum GemmPrec : int { GEMM_F32 = 0, GEMM_BF16 = 1, GEMM_F16 = 2 };
 //   position  s = sum_{i<=k} x_i               in [(q_min-q0)/dt, (q_max-q0)/dt]
 //   accel.    s = x_k - x_{k-1}, x_0 := v0     in [a_min dt, a_max dt]
 //   jerk      s = a_k - a_{k-1}, a_1 := 0      in [j_min dt^2, j_max dt^2]
-// (1-based steps; the jerk row of step 1 is identically zero and unused).
+// (1-based steps; the kernel's jerk row of step 1 is identically zero and its
+// bounds are widened to contain 0, so it is inert: jerk rows are steps 2..H).
 struct JointRowParams {
   float lb[4];
   float ub[4];

@@ -10,10 +10,15 @@
 #include <vector>
 
 #include "admm_kernels.h"
+#include "counter_ring.h"
 #include "kernel_args.h"
 #include "prism_proj.h"
 
-constexpr int kCounterRing = 1024;   // counter sets per handle (solves in flight), kXcdQueues each
+// Tile-queue counter sets per handle (kXcdQueues counters each). Solves take them
+// in turn; a set is reused only after the launch that last used it has finished
+// (its completion event is waited for on the new solve's stream), so any number
+// of solves may be in flight on any streams.
+constexpr int kCounterRing = 64;
 
 struct prism_proj_s {
   int H = 0, nj = 0, HQ = 0, device = 0;
@@ -25,8 +30,10 @@ struct prism_proj_s {
   void* frag_bf16 = nullptr;        // device: FP32 fragments then BF16 fragments
   void* frag_f16 = nullptr;         // device: FP32 fragments then FP16 fragments
   double* d_bounds = nullptr;       // device copy of bnd
-  int* d_counters = nullptr;        // ring of tile counters for early-exit solves
-  std::atomic<unsigned> next_counter{0};
+  int* d_counters = nullptr;        // ring of tile-queue counter sets
+  std::mutex ring_mu;               // guards ring and ring_ev
+  prism::CounterRing<kCounterRing> ring;
+  hipEvent_t ring_ev[kCounterRing] = {};   // completion of each set's last launch
   int f32_bytes = 0, b16_bytes = 0;
   std::mutex lit_mu;                              // guards lit
   std::vector<std::pair<double, double*>> lit;    // device factors of the printed iteration, per delta
@@ -48,8 +55,10 @@ prism_status_t validate_options(const prism_options_t* o);
 int kernel_blocks_per_cu(const void* fn, int lds_bytes);
 // Fills the solver fields of K (the caller sets samples, outputs, N, iters, jp and
 // the optional sampling / cost parts), clears the tile queues and launches fn.
-prism_status_t launch_solve(const prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
-                            SolveKernelFn fn, hipStream_t stream);
+// counters: kXcdQueues device ints owned by the caller, or null to take a set from
+// the handle's ring.
+prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                            SolveKernelFn fn, hipStream_t stream, int* counters = nullptr);
 prism_status_t check_device(const prism_proj_s* p);   // occupancy, cached per (kernel, LDS)
 int device_cus();
 

@@ -108,9 +108,10 @@ prism_status_t fill_joint_params(const prism_proj_s* p, const double* q0, const 
     const double amin = p->bnd[4 * nj + j], amax = p->bnd[5 * nj + j];
     const double jmin = p->bnd[6 * nj + j], jmax = p->bnd[7 * nj + j];
     const double q1 = q0[j] + dt * v0[j];
-    // first rows are fixed by x_1 = v0: they must already hold
-    if (v0[j] < vmin || v0[j] > vmax || q1 < qmin || q1 > qmax || amin > 0.0 || amax < 0.0 ||
-        jmin > 0.0 || jmax < 0.0)
+    // rows fixed by x_1 = v0 (velocity, position and acceleration of step 1) must
+    // already hold; jerk rows start at step 2 (eq. (jerk_stack)), so the jerk bounds
+    // need not contain 0
+    if (v0[j] < vmin || v0[j] > vmax || q1 < qmin || q1 > qmax || amin > 0.0 || amax < 0.0)
       return PRISM_EINFEASIBLE;
     JointRowParams& r = jp[j];
     r.lb[0] = (float)vmin;
@@ -145,8 +146,8 @@ int solve_lds_bytes(const prism_proj_s* p, int precision) {
   return solve_frag_bytes(p, precision) + kWaves * p->HQ * 64 * (int)sizeof(float);
 }
 
-prism_status_t launch_solve(const prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
-                            SolveKernelFn fn, hipStream_t stream) {
+prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                            SolveKernelFn fn, hipStream_t stream, int* counters) {
   const int tiles_per_joint = (K.N + kTileCols - 1) / kTileCols;
   const long long ntiles = (long long)tiles_per_joint * p->nj;
   if (ntiles > 0x7fffffff) return PRISM_EINVAL;
@@ -165,21 +166,44 @@ prism_status_t launch_solve(const prism_proj_s* p, SolveKernelArgs& K, const pri
   K.tol = o->tol;
   K.frag_f32_bytes = p->f32_bytes;
   K.frag_16_bytes = p->b16_bytes;
-  const unsigned slot = const_cast<prism_proj_s*>(p)->next_counter.fetch_add(1) % kCounterRing;
-  K.counter = p->d_counters + (size_t)slot * kXcdQueues;
-
   const int lds = solve_lds_bytes(p, o->precision);
   const int bpc = blocks_per_cu((const void*)fn, lds);
   const long long want = (ntiles + kWaves - 1) / kWaves;
   const long long cap = (long long)bpc * num_cus();
   const int grid = (int)std::max(1ll, std::min(want, cap));
 
-  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
-  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
-  void* params[] = {&K};
-  if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
+  auto enqueue = [&]() -> prism_status_t {
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
+    if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+    void* params[] = {&K};
+    if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) !=
+        hipSuccess)
+      return PRISM_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+    return PRISM_OK;
+  };
+  if (counters) {
+    K.counter = counters;
+    return enqueue();
+  }
+  // A counter set of the handle's ring: wait (on this stream) for the last launch that
+  // used it, launch, record this launch's completion. Under graph capture the event
+  // calls are skipped: a captured graph keeps its set and must not run concurrently
+  // with itself.
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap_st) != hipSuccess) return PRISM_EDEVICE;
+  const bool capturing = cap_st != hipStreamCaptureStatusNone;
+  std::lock_guard<std::mutex> lk(p->ring_mu);
+  const auto t = p->ring.take();
+  K.counter = p->d_counters + (size_t)t.slot * kXcdQueues;
+  if (!capturing && t.wait && hipStreamWaitEvent(stream, p->ring_ev[t.slot], 0) != hipSuccess)
     return PRISM_EDEVICE;
-  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  const prism_status_t st = enqueue();
+  if (st != PRISM_OK) return st;
+  if (!capturing) {
+    if (hipEventRecord(p->ring_ev[t.slot], stream) != hipSuccess) return PRISM_EDEVICE;
+    p->ring.recorded(t.slot);
+  }
   return PRISM_OK;
 }
 
@@ -311,6 +335,9 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
         hipMemset(p->d_counters, 0, sizeof(int) * kCounterRing * kXcdQueues) != hipSuccess)
       st = PRISM_EDEVICE;
   }
+  for (int i = 0; st == PRISM_OK && i < kCounterRing; ++i)
+    if (hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+      st = PRISM_EDEVICE;
   if (st != PRISM_OK) {
     prism_proj_destroy(p);
     return st;
@@ -325,6 +352,8 @@ void prism_proj_destroy(prism_proj_t p) {
   if (p->frag_f16) (void)hipFree(p->frag_f16);
   if (p->d_bounds) (void)hipFree(p->d_bounds);
   if (p->d_counters) (void)hipFree(p->d_counters);
+  for (hipEvent_t& e : p->ring_ev)
+    if (e) (void)hipEventDestroy(e);
   release_literal_factors(p);
   delete p;
 }

@@ -39,6 +39,32 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _on_device(t, device) -> bool:
+    return bool(t.is_cuda) and (device is None or t.device == device)
+
+
+def _check(t, name, shape, dtype, device, optional=True):
+    """Checks a tensor before its pointer goes to the library, which cannot: dtype,
+    contiguity, the exact shape, and the device (the GPU of the other tensors).
+    Raises ValueError naming the argument."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not _on_device(t, device):
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    return t
+
+
 def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -111,16 +137,26 @@ class Projector:
         MPC step first when warm_shift is set.
         """
         import torch
+        if samples is None or samples.ndim != 3:
+            raise ValueError("samples: expected a [N][H][n_joints] tensor")
         N = int(samples.shape[0])
-        assert samples.dtype == torch.float32 and samples.is_cuda and samples.is_contiguous()
-        assert tuple(samples.shape[1:]) == (self.H, self.nj)
         dev = samples.device
+        f32, i32 = torch.float32, torch.int32
+        traj, col, state = (N, self.H, self.nj), (N, self.nj), (N, self.nj, 4, self.H)
+        _check(samples, "samples", traj, f32, dev, optional=False)
         if out is None:
             out = torch.empty_like(samples)
         if r_primal is None:
-            r_primal = torch.empty((N, self.nj), dtype=torch.float32, device=dev)
+            r_primal = torch.empty(col, dtype=f32, device=dev)
         if r_dual is None:
-            r_dual = torch.empty((N, self.nj), dtype=torch.float32, device=dev)
+            r_dual = torch.empty(col, dtype=f32, device=dev)
+        _check(out, "out", traj, f32, dev)
+        _check(r_primal, "r_primal", col, f32, dev)
+        _check(r_dual, "r_dual", col, f32, dev)
+        _check(iters_out, "iters_out", col, i32, dev)
+        _check(x_warm, "x_warm", traj, f32, dev)
+        _check(state_warm, "state_warm", state, f32, dev)
+        _check(state_out, "state_out", state, f32, dev)
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
         a = L.SolveArgs()
@@ -149,16 +185,19 @@ class Projector:
         projection: it stops at a feasible point near the sample. Asynchronous on
         the stream. Returns (v_out [N][H][nj] float32, violation [N][nj] float64)."""
         import torch
+        if samples is None or samples.ndim != 3:
+            raise ValueError("samples: expected a [N][H][n_joints] tensor")
         N = int(samples.shape[0])
-        assert samples.dtype == torch.float32 and samples.is_cuda and samples.is_contiguous()
-        assert tuple(samples.shape[1:]) == (self.H, self.nj)
-        if x_init is not None:
-            assert x_init.dtype == torch.float32 and x_init.is_contiguous()
-            assert x_init.shape == samples.shape
+        dev = samples.device
+        traj = (N, self.H, self.nj)
+        _check(samples, "samples", traj, torch.float32, dev, optional=False)
+        _check(x_init, "x_init", traj, torch.float32, dev)
         if out is None:
             out = torch.empty_like(samples)
         if violation is None:
-            violation = torch.empty((N, self.nj), dtype=torch.float64, device=samples.device)
+            violation = torch.empty((N, self.nj), dtype=torch.float64, device=dev)
+        _check(out, "out", traj, torch.float32, dev)
+        _check(violation, "violation", (N, self.nj), torch.float64, dev)
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
         a = L.LiteralArgs()
@@ -178,22 +217,45 @@ class Projector:
     def plan_step(self, nu, sigma, N: int, seed: int, stream_id: int, q0, v0, theta_ref,
                   w_pos: float, w_vel: float, tau: float, eps: float, iters: int,
                   opts: Optional[L.Options] = None, samples_out=None, r_primal=None,
-                  r_dual=None, iters_out=None, workspace=None, stream=None):
+                  r_dual=None, iters_out=None, workspace=None, stream=None, outputs=None):
         """One optimizer iteration (prism_plan_step): draw N samples from
         N(nu, diag(sigma^2)) on the device, project, score, weight, update moments.
         nu, sigma, theta_ref: [H][nj] float32 on the GPU. Returns a dict of tensors
-        x, cost, omega, nu, var, best (and samples when samples_out is given)."""
+        x, cost, omega, nu, var, best (and samples when samples_out is given).
+
+        outputs: an earlier call's result dict whose x, cost, omega, nu, var, best
+        tensors are written again instead of new ones."""
         import torch
         dev = nu.device
-        x = torch.empty((N, self.H, self.nj), dtype=torch.float32, device=dev)
-        cost = torch.empty(N, dtype=torch.float64, device=dev)
-        omega = torch.empty(N, dtype=torch.float64, device=dev)
-        nu_out = torch.empty((self.H, self.nj), dtype=torch.float32, device=dev)
-        var_out = torch.empty_like(nu_out)
-        best = torch.empty(1, dtype=torch.int32, device=dev)
-        nbytes = int(L.lib().prism_plan_workspace_bytes(self.H, self.nj, int(N)))
+        N = int(N)
+        f32 = torch.float32
+        hj, traj, col = (self.H, self.nj), (N, self.H, self.nj), (N, self.nj)
+        _check(nu, "nu", hj, f32, dev, optional=False)
+        _check(sigma, "sigma", hj, f32, dev, optional=False)
+        _check(theta_ref, "theta_ref", hj, f32, dev, optional=False)
+        if outputs is None:
+            outputs = {"x": torch.empty(traj, dtype=f32, device=dev),
+                       "cost": torch.empty(N, dtype=torch.float64, device=dev),
+                       "omega": torch.empty(N, dtype=torch.float64, device=dev),
+                       "nu": torch.empty(hj, dtype=f32, device=dev),
+                       "var": torch.empty(hj, dtype=f32, device=dev),
+                       "best": torch.empty(1, dtype=torch.int32, device=dev)}
+        x = _check(outputs["x"], "x", traj, f32, dev, optional=False)
+        cost = _check(outputs["cost"], "cost", (N,), torch.float64, dev, optional=False)
+        omega = _check(outputs["omega"], "omega", (N,), torch.float64, dev, optional=False)
+        nu_out = _check(outputs["nu"], "nu_out", hj, f32, dev, optional=False)
+        var_out = _check(outputs["var"], "var_out", hj, f32, dev, optional=False)
+        best = _check(outputs["best"], "best", (1,), torch.int32, dev, optional=False)
+        _check(samples_out, "samples_out", traj, f32, dev)
+        _check(r_primal, "r_primal", col, f32, dev)
+        _check(r_dual, "r_dual", col, f32, dev)
+        _check(iters_out, "iters_out", col, torch.int32, dev)
+        nbytes = int(L.lib().prism_plan_workspace_bytes(self.H, self.nj, N))
         if workspace is None or workspace.numel() < nbytes:
             workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        if (workspace.dtype != torch.uint8 or not workspace.is_contiguous()
+                or workspace.device != dev):
+            raise ValueError("workspace: expected a contiguous uint8 tensor on the device")
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
         a = L.PlanArgs()
@@ -220,9 +282,13 @@ class Projector:
     def feasibility(self, v, q0, v0, out=None, stream=None):
         """FP64 per-column violations [N][nj][5]: position, velocity, acceleration, jerk, |x1-v0|."""
         import torch
+        if v is None or v.ndim != 3:
+            raise ValueError("v: expected a [N][H][n_joints] tensor")
         N = int(v.shape[0])
+        _check(v, "v", (N, self.H, self.nj), torch.float32, v.device, optional=False)
         if out is None:
             out = torch.empty((N, self.nj, 5), dtype=torch.float64, device=v.device)
+        _check(out, "out", (N, self.nj, 5), torch.float64, v.device)
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
         L.check(L.lib().prism_proj_feasibility(self._h, _ptr(v), N, q0a, v0a, _ptr(out),
@@ -274,15 +340,26 @@ class Batch:
         for i, r in enumerate(requests):
             P = r["proj"]
             x = r["samples"]
+            if x is None or x.ndim != 3:
+                raise ValueError(f"request {i}: samples must be a [N][H][n_joints] tensor")
             N = int(x.shape[0])
-            assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
-            assert tuple(x.shape[1:]) == (P.H, P.nj)
+            dev = x.device
+            f32 = torch.float32
+            traj, col, state = (N, P.H, P.nj), (N, P.nj), (N, P.nj, 4, P.H)
+            _check(x, f"request {i} samples", traj, f32, dev, optional=False)
             out = r.get("out")
             out = torch.empty_like(x) if out is None else out
             rp = r.get("r_primal")
-            rp = torch.empty((N, P.nj), dtype=torch.float32, device=x.device) if rp is None else rp
+            rp = torch.empty(col, dtype=f32, device=dev) if rp is None else rp
             rd = r.get("r_dual")
-            rd = torch.empty((N, P.nj), dtype=torch.float32, device=x.device) if rd is None else rd
+            rd = torch.empty(col, dtype=f32, device=dev) if rd is None else rd
+            _check(out, f"request {i} out", traj, f32, dev)
+            _check(rp, f"request {i} r_primal", col, f32, dev)
+            _check(rd, f"request {i} r_dual", col, f32, dev)
+            _check(r.get("iters_out"), f"request {i} iters_out", col, torch.int32, dev)
+            _check(r.get("x_warm"), f"request {i} x_warm", traj, f32, dev)
+            _check(r.get("state_warm"), f"request {i} state_warm", state, f32, dev)
+            _check(r.get("state_out"), f"request {i} state_out", state, f32, dev)
             q0a = L.dbl_array(np.broadcast_to(np.asarray(r["q0"], dtype=np.float64), (P.nj,)))
             v0a = L.dbl_array(np.broadcast_to(np.asarray(r["v0"], dtype=np.float64), (P.nj,)))
             keep += [q0a, v0a]

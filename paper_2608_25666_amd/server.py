@@ -59,6 +59,17 @@ class Server:
                iters_out=None) -> int:
         P = self._ctrl.get(ctrl)          # unknown ids are rejected by the library
         nj = P.nj if P is not None else int(np.asarray(q0).size)
+        if P is not None:
+            import torch
+            from .projector import _check
+            if samples is None or samples.ndim != 3:
+                raise ValueError("samples: expected a [N][H][n_joints] tensor")
+            N, dev, f32 = int(samples.shape[0]), samples.device, torch.float32
+            _check(samples, "samples", (N, P.H, P.nj), f32, dev, optional=False)
+            _check(out, "out", (N, P.H, P.nj), f32, dev, optional=False)
+            _check(r_primal, "r_primal", (N, P.nj), f32, dev)
+            _check(r_dual, "r_dual", (N, P.nj), f32, dev)
+            _check(iters_out, "iters_out", (N, P.nj), torch.int32, dev)
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (nj,)))
         r = L.ServeRequest()

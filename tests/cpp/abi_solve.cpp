@@ -1,9 +1,12 @@
 // A native consumer of the C ABI (include/prism_proj.h), with no Python or
 // PyTorch involved: reads one projection problem from a binary file, allocates
-// device buffers with the HIP runtime, calls prism_proj_create_ex,
-// prism_proj_solve_ex and prism_proj_feasibility, and writes the results.
+// device buffers with the HIP runtime, calls the library, and writes the results.
+// Mode 0: prism_proj_create_ex, prism_proj_solve_ex, prism_proj_feasibility.
+// Mode 1 (the plain signatures): prism_proj_create (weights ignored),
+// prism_proj_set_options, prism_proj_solve, prism_proj_feasibility; the
+// iteration counts are then not reported (written as -1).
 //
-// Input (little-endian): int32 H, nj, N, iters, precision; float64 dt, rho,
+// Input (little-endian): int32 H, nj, N, iters, precision, mode; float64 dt, rho,
 // weights[4]; float32 alpha, tol; float64 bounds[8][nj] (q_min, q_max, v_min,
 // v_max, a_min, a_max, j_min, j_max), q0[nj], v0[nj]; float32 samples[N][H][nj].
 // Output: float32 x[N][H][nj], r_primal[N][nj], r_dual[N][nj]; int32
@@ -45,12 +48,13 @@ int main(int argc, char** argv) {
   }
   std::FILE* f = std::fopen(argv[1], "rb");
   if (!f) return 1;
-  int32_t hdr[5];
+  int32_t hdr[6];
   double dtrho[2], w[4];
   float at[2];
-  if (!rd(f, hdr, 5) || !rd(f, dtrho, 2) || !rd(f, w, 4) || !rd(f, at, 2)) return 2;
+  if (!rd(f, hdr, 6) || !rd(f, dtrho, 2) || !rd(f, w, 4) || !rd(f, at, 2)) return 2;
   const int H = hdr[0], nj = hdr[1], N = hdr[2], iters = hdr[3], precision = hdr[4];
-  if (H < 2 || nj < 1 || N < 1) return 2;
+  const int mode = hdr[5];
+  if (H < 2 || nj < 1 || N < 1 || (mode != 0 && mode != 1)) return 2;
   std::vector<double> b(8 * (size_t)nj), q0(nj), v0(nj);
   const size_t nx = (size_t)N * H * nj, nc = (size_t)N * nj;
   std::vector<float> xs(nx);
@@ -62,7 +66,10 @@ int main(int argc, char** argv) {
   prism_bounds_t bounds = {&b[0 * nj], &b[1 * nj], &b[2 * nj], &b[3 * nj],
                            &b[4 * nj], &b[5 * nj], &b[6 * nj], &b[7 * nj]};
   prism_proj_t p = nullptr;
-  CHECK_PRISM(prism_proj_create_ex(H, nj, dtrho[0], &bounds, dtrho[1], w, &p));
+  if (mode == 0)
+    CHECK_PRISM(prism_proj_create_ex(H, nj, dtrho[0], &bounds, dtrho[1], w, &p));
+  else
+    CHECK_PRISM(prism_proj_create(H, nj, dtrho[0], &bounds, dtrho[1], &p));
   prism_options_t o;
   prism_options_default(&o);
   o.precision = precision;
@@ -83,18 +90,24 @@ int main(int argc, char** argv) {
   hipStream_t st;
   CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
 
-  prism_solve_args_t a = {};
-  a.v_samples = d_x;
-  a.N = N;
-  a.iters = iters;
-  a.q0 = q0.data();
-  a.v0 = v0.data();
-  a.v_out = d_out;
-  a.r_primal = d_rp;
-  a.r_dual = d_rd;
-  a.iters_out = d_it;
-  a.opts = &o;
-  CHECK_PRISM(prism_proj_solve_ex(p, &a, st));
+  if (mode == 0) {
+    prism_solve_args_t a = {};
+    a.v_samples = d_x;
+    a.N = N;
+    a.iters = iters;
+    a.q0 = q0.data();
+    a.v0 = v0.data();
+    a.v_out = d_out;
+    a.r_primal = d_rp;
+    a.r_dual = d_rd;
+    a.iters_out = d_it;
+    a.opts = &o;
+    CHECK_PRISM(prism_proj_solve_ex(p, &a, st));
+  } else {
+    CHECK_HIP(hipMemset(d_it, 0xff, nc * sizeof(int32_t)));
+    CHECK_PRISM(prism_proj_set_options(p, &o));
+    CHECK_PRISM(prism_proj_solve(p, d_x, N, q0.data(), v0.data(), iters, d_out, d_rp, d_rd, st));
+  }
   CHECK_PRISM(prism_proj_feasibility(p, d_out, N, q0.data(), v0.data(), d_v, st));
   CHECK_HIP(hipStreamSynchronize(st));
 

@@ -14,7 +14,7 @@ a cost within that tolerance of the minimum.
 import numpy as np
 import pytest
 
-from oracle import planner
+from oracle import admm, planner
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -116,4 +116,71 @@ def test_plan_step_rejects_bad_arguments():
     from paper_2608_25666_amd import _lib as L
     n = L.lib().prism_plan_workspace_bytes(P.H, P.nj, 16)
     assert n > 16
+    P.close()
+
+
+# residual-driven projection of the reduced forms against the oracle at the same
+# per-column counts (tests/test_gpu_forms.py states and derives it)
+TOL_REDUCED_RESIDUAL = 5e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("H,dt", [(20, 0.05), (50, 0.02), (100, 0.02)])
+def test_plan_step_bench_settings(H, dt, prec):
+    """The optimizer step at bench.py --workload plan's options (default block weights,
+    alpha 1.8, residual <= 1e-3 checked every 10, reduced forms with 10 FP32 iterations
+    after convergence), at chunk sizes 5, 13 and 25: the two-wave kernels (FP32 up to
+    chunk 13, 16-bit up to 12) and the one-wave ones. Checked:
+    * drawn samples against the oracle's draw (1e-5, FP32 ln/cos);
+    * projected samples against the oracle's projection of its own draw run to the
+      reported per-column counts (FP32 bar 1e-4; reduced forms their residual-mode bar);
+    * costs, weights, moments and the lowest-cost index against the oracle's functions
+      applied to the GPU's own projected samples and costs: costs 2e-5 relative (FP32
+      sums over H steps), weights 1e-12 relative (both FP64 from the same costs),
+      moments 1e-6 absolute (FP64 sums stored in FP32)."""
+    import torch
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16, PREC_FP32
+    p = {"fp32": PREC_FP32, "fp16": PREC_FP16, "bf16": PREC_BF16}[prec]
+    N, nj = 64, 12
+    P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup(N=N, H=H, nj=nj, dt=dt, seed=H)
+    sigma_t.fill_(0.5)
+    sigma = np.full((H, nj), 0.5)
+    kw = dict(w_pos=10.0, w_vel=0.1, tau=1.0, eps=1e-3)
+    drawn = torch.empty((N, H, nj), dtype=torch.float32, device="cuda")
+    it = torch.empty((N, nj), dtype=torch.int32, device="cuda")
+    rp = torch.empty((N, nj), dtype=torch.float32, device="cuda")
+    rd = torch.empty_like(rp)
+    o = options(precision=p, alpha=1.8, tol=1e-3, check_every=10,
+                fp32_tail=0 if prec == "fp32" else 10)
+    g = P.plan_step(nu_t, sigma_t, N, seed=7, stream_id=3, q0=r.q0, v0=r.v0, theta_ref=ref_t,
+                    iters=20000, opts=o, samples_out=drawn, iters_out=it, r_primal=rp,
+                    r_dual=rd, **kw)
+    torch.cuda.synchronize()
+    xg = g["x"].cpu().numpy().astype(np.float64)
+    itg = it.cpu().numpy()
+    assert np.all(np.maximum(rp.cpu().numpy(), rd.cpu().numpy()) <= 1e-3)
+    nu32 = nu.astype(np.float32).astype(np.float64)
+    sg32 = sigma.astype(np.float32).astype(np.float64)
+    ref32 = ref.astype(np.float32).astype(np.float64)
+    xs = planner.draw(nu32, sg32, N, 7, 3)
+    err_s = np.abs(drawn.cpu().numpy() - xs).max()
+    O = admm.solve_request(xs, H, dt, r.bounds, r.q0, r.v0, iters=itg, alpha=1.8,
+                           weights=P.weights)
+    err_x = np.abs(xg - O.x).max()
+    c = g["cost"].cpu().numpy()
+    w = g["omega"].cpu().numpy()
+    c_o = planner.tracking_cost(xg, r.q0, dt, ref32, kw["w_pos"], kw["w_vel"])
+    w_o = planner.softmax_weights(c, kw["tau"])
+    m_o, v_o = planner.moments(xg, w, kw["eps"])
+    print(f"H={H} {prec}: iters {itg.min()}..{itg.max()}; drawn {err_s:.1e}, projected "
+          f"{err_x:.2e}, cost rel {np.abs(c / c_o - 1).max():.1e}, weight rel "
+          f"{np.abs(w / w_o - 1).max():.1e}, moments {np.abs(g['nu'].cpu().numpy() - m_o).max():.1e}"
+          f" / {np.abs(g['var'].cpu().numpy() - v_o).max():.1e}")
+    assert err_s <= 1e-5
+    assert err_x <= (1e-4 if prec == "fp32" else TOL_REDUCED_RESIDUAL)
+    np.testing.assert_allclose(c, c_o, rtol=2e-5)
+    np.testing.assert_allclose(w, w_o, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(g["nu"].cpu().numpy(), m_o, atol=1e-6)
+    np.testing.assert_allclose(g["var"].cpu().numpy(), v_o, atol=1e-6)
+    assert int(g["best"].cpu().numpy()[0]) == int(np.argmin(c))
     P.close()
