@@ -59,7 +59,8 @@ typedef enum {
   PRISM_EDEVICE = -3,       /* a HIP call failed, or wrong device current */
   PRISM_EINFEASIBLE = -4,   /* a necessary boundary condition fails (see solve) */
   PRISM_EBUSY = -5,         /* server admission refused (budget or queue full) */
-  PRISM_EUNSUPPORTED = -6   /* combination not built into this library */
+  PRISM_EUNSUPPORTED = -6,  /* combination not built into this library */
+  PRISM_ETOOLARGE = -7      /* request exceeds a fixed capacity (prism_plan_step_static) */
 } prism_status_t;
 
 /* Joint-wise limits (Sec. III-D "Velocity bounds": joint-wise limit vectors).
@@ -313,6 +314,24 @@ size_t prism_plan_workspace_bytes(int H, int n_joints, int N);
  * prism_proj_solve); nothing is enqueued on error. Calls that share a workspace
  * must be ordered (same stream). */
 prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream);
+
+/* prism_plan_step_static -- prism_plan_step for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. It makes no allocation of any kind (no hipMalloc/hipFree, no
+ * library allocator): the workspace and the solve's tile-queue counters live in a
+ * static device array of PRISM_PLAN_STATIC_WORKSPACE_BYTES (+ 256 bytes for the
+ * counters) that each GPU the library runs on holds until the process ends.
+ * a->workspace and a->workspace_bytes are ignored; every other argument, check and
+ * result is that of prism_plan_step (same kernels, bit-identical outputs).
+ * Returns PRISM_ETOOLARGE, with nothing enqueued, when
+ * prism_plan_workspace_bytes(H, n_joints, N) exceeds PRISM_PLAN_STATIC_WORKSPACE_BYTES
+ * (N <= 92 666 samples at 12 joints and H = 50). All calls on one GPU share
+ * its array: calls that overlap in time on that GPU (different streams, or other
+ * threads) race and give wrong results; calls ordered on one stream are safe. The
+ * counters are cleared by a kernel at the start of every call. */
+#define PRISM_PLAN_STATIC_WORKSPACE_BYTES ((size_t)8 << 20)
+prism_status_t prism_plan_step_static(prism_proj_t p, const prism_plan_args_t* a,
+                                      hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * prism_proj_literal -- the Bregman iteration exactly as Sec. III-D prints it

@@ -19,6 +19,8 @@ PRISM_EDEVICE = -3
 PRISM_EINFEASIBLE = -4
 PRISM_EBUSY = -5
 PRISM_EUNSUPPORTED = -6
+PRISM_ETOOLARGE = -7
+PLAN_STATIC_WORKSPACE_BYTES = 8 << 20
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 MAX_H = 128
@@ -155,6 +157,7 @@ def load(path: str = LIB_PATH):
                                         C.c_void_p]),
         "prism_plan_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
         "prism_plan_step": (st, [H, C.POINTER(PlanArgs), C.c_void_p]),
+        "prism_plan_step_static": (st, [H, C.POINTER(PlanArgs), C.c_void_p]),
         "prism_proj_literal": (st, [H, C.POINTER(LiteralArgs), C.c_void_p]),
         "prism_server_config_default": (None, [C.POINTER(ServerConfig)]),
         "prism_server_create": (st, [C.POINTER(ServerConfig), C.POINTER(H)]),

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "admm_kernels.h"
 #include "prism_internal.h"
@@ -123,31 +124,54 @@ SolveKernelFn pick_plan_kernel(int HQ, int precision) {
 
 bool fin(double v) { return std::isfinite(v); }
 
-}  // namespace
+// Scratch of prism_plan_step_static, one copy per GPU for the life of the process:
+// the solve's tile-queue counters (cleared by a kernel before every launch), then
+// the workspace of prism_plan_step (every byte of it written before it is read).
+constexpr size_t kStaticCounterBytes = 256;
+constexpr size_t kStaticWorkspaceBytes = PRISM_PLAN_STATIC_WORKSPACE_BYTES;
+static_assert(kXcdQueues * sizeof(int) <= kStaticCounterBytes, "counters fit");
+static __device__ __align__(256) unsigned char scratch[kStaticCounterBytes + kStaticWorkspaceBytes];
 
-extern "C" {
+// Device address of `scratch` per device, looked up once per device with that device
+// current (host code must not use the array's name: it is a host-side stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
 
-size_t prism_plan_workspace_bytes(int H, int n_joints, int N) {
-  if (H < 2 || H > PRISM_MAX_H || n_joints < 1 || n_joints > PRISM_MAX_JOINTS || N < 1) return 0;
-  const size_t E = (size_t)H * n_joints;
-  return align256((size_t)N * n_joints * sizeof(float)) + 2 * align256((size_t)N * sizeof(double)) +
-         align256(sizeof(int)) + align256((size_t)moment_blocks(N) * E * 2 * sizeof(double));
+prism_status_t static_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return PRISM_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PRISM_EDEVICE;
+    g_scratch[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return PRISM_OK;
 }
 
-prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream) {
-  if (!p || !a) return PRISM_EINVAL;
+}  // namespace
+
+extern "C" size_t prism_plan_workspace_bytes(int H, int n_joints, int N);
+
+namespace {
+
+// One optimizer iteration with the given workspace and, if not null, the given
+// tile-queue counters (else a set of the handle's ring).
+prism_status_t plan_step_impl(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream,
+                              void* workspace, size_t workspace_bytes, int* counters) {
   const prism_options_t* o = a->opts ? a->opts : &p->opts;
   prism_status_t st = validate_options(o);
   if (st != PRISM_OK) return st;
   if (a->N < 1 || a->iters < 0 || !a->q0 || !a->v0 || !a->nu || !a->sigma || !a->theta_ref ||
-      !a->x_out || !a->nu_out || !a->var_out || !a->workspace)
+      !a->x_out || !a->nu_out || !a->var_out)
     return PRISM_EINVAL;
   if (!fin(a->tau) || a->tau <= 0.0f || !fin(a->eps) || a->eps < 0.0f || !fin(a->w_pos) ||
       a->w_pos < 0.0f || !fin(a->w_vel) || a->w_vel < 0.0f)
     return PRISM_EINVAL;
   if ((long long)a->N * p->H * p->nj > (1ll << 40)) return PRISM_EINVAL;
   const size_t need = prism_plan_workspace_bytes(p->H, p->nj, a->N);
-  if (need == 0 || a->workspace_bytes < need) return PRISM_EINVAL;
+  if (need == 0 || workspace_bytes < need) return PRISM_EINVAL;
   SolveKernelArgs K{};
   st = fill_joint_params(p, a->q0, a->v0, K.jp);
   if (st != PRISM_OK) return st;
@@ -157,7 +181,7 @@ prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipSt
   if (!fn) return PRISM_EUNSUPPORTED;
 
   // carve the workspace
-  char* w = static_cast<char*>(a->workspace);
+  char* w = static_cast<char*>(workspace);
   float* cost_col = reinterpret_cast<float*>(w);
   w += align256((size_t)a->N * p->nj * sizeof(float));
   double* cost = a->cost ? a->cost : reinterpret_cast<double*>(w);
@@ -189,7 +213,7 @@ prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipSt
   K.cost.w_pos = a->w_pos;
   K.cost.w_vel = a->w_vel;
   K.cost.dt = (float)p->dt;
-  st = launch_solve(p, K, o, fn, stream);
+  st = launch_solve(p, K, o, fn, stream, counters);
   if (st != PRISM_OK) return st;
 
   hipLaunchKernelGGL(plan_weights_kernel, dim3(1), dim3(kWeightThreads), 0, stream, cost_col, a->N,
@@ -206,6 +230,40 @@ prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipSt
                      a->var_out);
   if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prism_plan_workspace_bytes(int H, int n_joints, int N) {
+  if (H < 2 || H > PRISM_MAX_H || n_joints < 1 || n_joints > PRISM_MAX_JOINTS || N < 1) return 0;
+  const size_t E = (size_t)H * n_joints;
+  return align256((size_t)N * n_joints * sizeof(float)) + 2 * align256((size_t)N * sizeof(double)) +
+         align256(sizeof(int)) + align256((size_t)moment_blocks(N) * E * 2 * sizeof(double));
+}
+
+prism_status_t prism_plan_step(prism_proj_t p, const prism_plan_args_t* a, hipStream_t stream) {
+  if (!p || !a) return PRISM_EINVAL;
+  if (!a->workspace) return PRISM_EINVAL;
+  return plan_step_impl(p, a, stream, a->workspace, a->workspace_bytes, nullptr);
+}
+
+prism_status_t prism_plan_step_static(prism_proj_t p, const prism_plan_args_t* a,
+                                      hipStream_t stream) {
+  if (!p || !a) return PRISM_EINVAL;
+  if (a->N >= 1) {
+    const size_t need = prism_plan_workspace_bytes(p->H, p->nj, a->N);
+    if (need > kStaticWorkspaceBytes) return PRISM_ETOOLARGE;
+  }
+  prism_status_t st = check_device(p);
+  if (st != PRISM_OK) return st;
+  char* base = nullptr;
+  st = static_scratch(p->device, &base);
+  if (st != PRISM_OK) return st;
+  // the tile-queue counters first, then the workspace carve of prism_plan_step
+  return plan_step_impl(p, a, stream, base + kStaticCounterBytes, kStaticWorkspaceBytes,
+                        reinterpret_cast<int*>(base));
 }
 
 }  // extern "C"

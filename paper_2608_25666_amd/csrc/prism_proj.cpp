@@ -233,6 +233,7 @@ const char* prism_status_str(prism_status_t s) {
     case PRISM_EINFEASIBLE: return "infeasible boundary condition";
     case PRISM_EBUSY: return "busy (admission refused)";
     case PRISM_EUNSUPPORTED: return "unsupported configuration";
+    case PRISM_ETOOLARGE: return "request exceeds a fixed capacity";
   }
   return "unknown status";
 }

@@ -217,14 +217,16 @@ class Projector:
     def plan_step(self, nu, sigma, N: int, seed: int, stream_id: int, q0, v0, theta_ref,
                   w_pos: float, w_vel: float, tau: float, eps: float, iters: int,
                   opts: Optional[L.Options] = None, samples_out=None, r_primal=None,
-                  r_dual=None, iters_out=None, workspace=None, stream=None, outputs=None):
+                  r_dual=None, iters_out=None, workspace=None, stream=None, static=False,
+                  outputs=None):
         """One optimizer iteration (prism_plan_step): draw N samples from
         N(nu, diag(sigma^2)) on the device, project, score, weight, update moments.
         nu, sigma, theta_ref: [H][nj] float32 on the GPU. Returns a dict of tensors
         x, cost, omega, nu, var, best (and samples when samples_out is given).
 
-        outputs: an earlier call's result dict whose x, cost, omega, nu, var, best
-        tensors are written again instead of new ones."""
+        static=True calls prism_plan_step_static (no workspace: the library's static
+        device scratch). outputs: an earlier call's result dict whose x, cost, omega,
+        nu, var, best tensors are written again instead of new ones (no allocation)."""
         import torch
         dev = nu.device
         N = int(N)
@@ -250,12 +252,15 @@ class Projector:
         _check(r_primal, "r_primal", col, f32, dev)
         _check(r_dual, "r_dual", col, f32, dev)
         _check(iters_out, "iters_out", col, torch.int32, dev)
-        nbytes = int(L.lib().prism_plan_workspace_bytes(self.H, self.nj, N))
-        if workspace is None or workspace.numel() < nbytes:
-            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-        if (workspace.dtype != torch.uint8 or not workspace.is_contiguous()
-                or workspace.device != dev):
-            raise ValueError("workspace: expected a contiguous uint8 tensor on the device")
+        if static:
+            workspace = None
+        else:
+            nbytes = int(L.lib().prism_plan_workspace_bytes(self.H, self.nj, N))
+            if workspace is None or workspace.numel() < nbytes:
+                workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            if (workspace.dtype != torch.uint8 or not workspace.is_contiguous()
+                    or workspace.device != dev):
+                raise ValueError("workspace: expected a contiguous uint8 tensor on the device")
         q0a = L.dbl_array(np.broadcast_to(np.asarray(q0, dtype=np.float64), (self.nj,)))
         v0a = L.dbl_array(np.broadcast_to(np.asarray(v0, dtype=np.float64), (self.nj,)))
         a = L.PlanArgs()
@@ -270,9 +275,17 @@ class Projector:
         a.r_primal = None if r_primal is None else r_primal.data_ptr()
         a.r_dual = None if r_dual is None else r_dual.data_ptr()
         a.iters_out = None if iters_out is None else iters_out.data_ptr()
-        a.workspace, a.workspace_bytes = workspace.data_ptr(), int(workspace.numel())
+        if workspace is None:
+            a.workspace, a.workspace_bytes = None, 0
+        else:
+            a.workspace, a.workspace_bytes = workspace.data_ptr(), int(workspace.numel())
         a.opts = C.pointer(opts) if opts is not None else C.POINTER(L.Options)()
-        L.check(L.lib().prism_plan_step(self._h, C.byref(a), _stream(stream)), "prism_plan_step")
+        if static:
+            L.check(L.lib().prism_plan_step_static(self._h, C.byref(a), _stream(stream)),
+                    "prism_plan_step_static")
+        else:
+            L.check(L.lib().prism_plan_step(self._h, C.byref(a), _stream(stream)),
+                    "prism_plan_step")
         out = {"x": x, "cost": cost, "omega": omega, "nu": nu_out, "var": var_out, "best": best,
                "workspace": workspace}
         if samples_out is not None:
