@@ -37,13 +37,20 @@ def residual_margin(O, H, dt, bounds, q0, v0, iters):
 
 def check_residual_mode(x, rp, rd, it, rows, samples, H, dt, bounds, q0, v0, *, tol,
                         check_every, cap, alpha, weights, rho=1.0, xbar=1e-4,
-                        check_stops=True, label=""):
+                        check_stops=True, label="", joints=None):
     """x, rp, rd, it: the GPU results of the sampled rows `rows` (whole tiles of the
     batch, in order); samples: the whole batch [N][H][nj]. check_stops: compare the
     stop points with the oracle's residuals (FP32 form only: a reduced-precision run
     follows a different path, so the oracle's residual at the same count says nothing
-    about its stop). Returns a dict of figures."""
+    about its stop). joints: check only these joints (columns are independent per
+    joint). Returns a dict of figures."""
     rows = np.asarray(rows)
+    if joints is not None:
+        joints = np.asarray(joints)
+        x, rp, rd, it = x[:, :, joints], rp[:, joints], rd[:, joints], it[:, joints]
+        samples = samples[:, :, joints]
+        bounds = bounds.subset(joints)
+        q0, v0 = np.asarray(q0)[joints], np.asarray(v0)[joints]
     S = samples[rows]
     res = np.maximum(rp, rd)
     assert np.all(res <= tol), f"{label}: a reported residual is above tol"

@@ -3,10 +3,12 @@
 Stated tolerances (rad/s, max-abs against the FP64 oracle at the same count):
 * FP32 form: 1e-4.
 * FP16 GEMM operands with the last 10 iterations in FP32: 5e-4.
-* BF16 GEMM operands with the last 10 iterations in FP32: 3e-2.
+* BF16 GEMM operands with the last 10 iterations in FP32: 2e-2.
   BF16 keeps 8 significant bits, so each x-update rounds the defect d at 2^-9
   relative; at a fixed count the iterates drift from the FP64 ones by that
-  amount times the contraction history.
+  amount times the contraction history. Measured on the GPU: 4.1e-3 (12 x 64,
+  H = 20, 200 iterations) and 7.8e-3 (12 x 8192, H = 100, 100 iterations); an
+  FP64 model of the same rounding gave up to 1.3e-2 at H = 50; the bar is 2e-2.
 * At convergence every form reaches the exact projection: the incremental
   update x += K d only rounds d, and d -> 0 at the fixed point, so the GEMM
   precision does not move the fixed point (max-abs 1e-4 to x*).
@@ -21,10 +23,13 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_F16_TAIL = 5e-4
-TOL_BF16_TAIL = 3e-2
-# residual mode, reduced GEMM until the tile meets tol, then 10 FP32 iterations: x
-# against the oracle run to the same per-column counts
-TOL_REDUCED_RESIDUAL = 5e-3
+TOL_BF16_TAIL = 2e-2
+# Residual mode, reduced GEMM until the tile meets tol, then 10 FP32 iterations: x
+# against the oracle run to the same per-column counts. Both lie within the residual
+# tolerance of the same projection by different paths; the largest difference measured
+# over the residual-mode tests (H = 20, 50, 100; solve and optimizer step) is 1.8e-3
+# (BF16) and 5.2e-4 (FP16); the stated bar is about twice the former.
+TOL_REDUCED_RESIDUAL = 4e-3
 
 
 def _run(req, iters, opts, samples=None, **kw):
@@ -255,8 +260,8 @@ def test_long_horizon_bench_settings_sampled(prec):
     """The long-horizon launch as the benchmark runs it: 8192 samples x 12 joints, H = 100
     (the exact-fit chunk-25 single-solve kernel), the default block weights, alpha 1.8,
     residual <= 1e-3 checked every 10, reduced forms with 10 FP32 iterations after
-    convergence. Three sampled tiles per joint against the oracle run to the reported
-    counts."""
+    convergence. The first and last tiles of four joints against the oracle run to the
+    reported counts (every column of the launch must meet the tolerance)."""
     import torch
     from paper_2608_25666_amd import Projector, options, PREC_BF16, PREC_FP16, PREC_FP32
     from stops import check_residual_mode
@@ -269,14 +274,17 @@ def test_long_horizon_bench_settings_sampled(prec):
                 fp32_tail=0 if prec == "fp32" else 10)
     out, rp, rd = P.solve(xs, r.q0, r.v0, 20000, opts=o, iters_out=it)
     torch.cuda.synchronize()
-    rows = np.r_[np.arange(0, 16), np.arange(4096, 4112), np.arange(8176, 8192)]
+    rows = np.r_[np.arange(0, 16), np.arange(8176, 8192)]
     res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
     assert np.all(res <= 1e-3)
+    itg = it.cpu().numpy()
+    joints = [int(np.argmax(itg.max(axis=0))), 0, 5, 11]      # the slowest joint first
     check_residual_mode(out.cpu().numpy()[rows], rp.cpu().numpy()[rows], rd.cpu().numpy()[rows],
-                        it.cpu().numpy()[rows], rows, r.samples, r.H, r.dt, r.bounds, r.q0, r.v0,
+                        itg[rows], rows, r.samples, r.H, r.dt, r.bounds, r.q0, r.v0,
                         tol=1e-3, check_every=10, cap=20000, alpha=1.8, weights=P.weights,
                         xbar=1e-4 if prec == "fp32" else TOL_REDUCED_RESIDUAL,
-                        check_stops=prec == "fp32", label=f"long horizon {prec}")
+                        check_stops=prec == "fp32", label=f"long horizon {prec}",
+                        joints=sorted(set(joints)))
     P.close()
 
 

@@ -121,7 +121,7 @@ def test_plan_step_rejects_bad_arguments():
 
 # residual-driven projection of the reduced forms against the oracle at the same
 # per-column counts (tests/test_gpu_forms.py states and derives it)
-TOL_REDUCED_RESIDUAL = 5e-3
+TOL_REDUCED_RESIDUAL = 4e-3
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
@@ -141,7 +141,7 @@ def test_plan_step_bench_settings(H, dt, prec):
     import torch
     from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16, PREC_FP32
     p = {"fp32": PREC_FP32, "fp16": PREC_FP16, "bf16": PREC_BF16}[prec]
-    N, nj = 64, 12
+    N, nj = (64, 12) if H <= 50 else (32, 4)      # the oracle's cost grows with H^2
     P, r, nu, sigma, ref, nu_t, sigma_t, ref_t = _setup(N=N, H=H, nj=nj, dt=dt, seed=H)
     sigma_t.fill_(0.5)
     sigma = np.full((H, nj), 0.5)
@@ -174,7 +174,8 @@ def test_plan_step_bench_settings(H, dt, prec):
     m_o, v_o = planner.moments(xg, w, kw["eps"])
     print(f"H={H} {prec}: iters {itg.min()}..{itg.max()}; drawn {err_s:.1e}, projected "
           f"{err_x:.2e}, cost rel {np.abs(c / c_o - 1).max():.1e}, weight rel "
-          f"{np.abs(w / w_o - 1).max():.1e}, moments {np.abs(g['nu'].cpu().numpy() - m_o).max():.1e}"
+          f"{np.abs(w - w_o).max() / w_o.max():.1e}, moments "
+          f"{np.abs(g['nu'].cpu().numpy() - m_o).max():.1e}"
           f" / {np.abs(g['var'].cpu().numpy() - v_o).max():.1e}")
     assert err_s <= 1e-5
     assert err_x <= (1e-4 if prec == "fp32" else TOL_REDUCED_RESIDUAL)

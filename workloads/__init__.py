@@ -14,6 +14,7 @@ from .recipes import (  # noqa: F401
     long_horizon_batch,
     uneven_requests,
     serving_controllers,
+    poisson_arrivals,
     controller_samples,
     sigma_eff_workload,
     make_request,

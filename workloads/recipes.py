@@ -192,6 +192,20 @@ def serving_controllers(seed: int = 0, n_controllers: int = 32, rate_hz: float =
     return ctrls
 
 
+def poisson_arrivals(n_controllers: int, rate_hz: float, duration_s: float,
+                     seed: int = 1) -> List[np.ndarray]:
+    """Poisson arrival times (seconds, ascending, < duration_s) for each of
+    n_controllers at rate_hz: exponential gaps from their own generator, so the same
+    controllers can be driven at several rates."""
+    rng = np.random.Generator(np.random.PCG64(seed * 7 + int(round(rate_hz * 1000))))
+    out = []
+    for _ in range(n_controllers):
+        gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * duration_s * 2) + 16)
+        t = np.cumsum(gaps)
+        out.append(t[t < duration_s])
+    return out
+
+
 def controller_samples(ctrl: Controller, step: int, noise: float = 0.5,
                        N: Optional[int] = None) -> np.ndarray:
     """Samples for a controller's request number ``step``: base shifted by ``step`` steps + noise."""
