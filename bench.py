@@ -1,36 +1,35 @@
 #!/usr/bin/env python3
-"""Benchmark: projected trajectories per second at residual <= 1e-3 on one MI355X.
+"""Benchmark: projected trajectories per second at residual <= 1e-3 on one MI355X,
+with p50/p99 request latency.
 
-Workload (default): 2 arms x 6 joints = 12 joints, N = 2048 sampled velocity
-trajectories, horizon H = 50, dt = 0.02 s, |q| <= 2 pi, |v| <= 3.14, |a| <= 8,
-|j| <= 60; samples = smooth three-sinusoid base + N(0, 0.5^2) noise; rho = 1.
-A step projects the whole batch until every 16-sample group of each joint has
-max(r_primal, r_dual) <= 1e-3 (checked every 10 iterations, capped at 20000).
-Inputs are resident in HBM before timing starts.
+Default run (what `python bench.py --gpus 1 --steps K --warmup W` prints as one JSON
+line):
+* value: the uneven batch -- 64 requests with H in {20, 50, 100}, N in {128, 512,
+  2048, 4096}, 6 or 12 joints, dt in {0.02, 0.05}, each with its own factor --
+  projected in one prism_proj_solve_batch call per step, FP32, every column to
+  max(r_primal, r_dual) <= 1e-3 (checked every 10, capped at 20000), timed over K
+  steps after W warm-up steps; the BF16 and FP16 forms (reduced GEMM until
+  convergence, then 10 FP32 iterations) side by side; roofline of the batch kernel
+  from HIP events on its stream;
+* workloads.long_horizon: 8192 samples x 12 joints, H = 100, dt = 0.02 (single solve),
+  all three forms, each with its roofline;
+* workloads.mpc: 2048 samples x 12 joints, H = 50, dt = 0.02 (single solve), all
+  three forms, each with its roofline;
+* workloads.serving: 32 controllers with the uneven requests' sizes issue Poisson
+  requests at 20 Hz each for 60 s into the continuous-batching server (warm start by
+  shift, HBM-budget admission): served trajectories/s and p50/p99 request latency
+  (arrival to completion) for FP32 and BF16 + FP32 tail; the top-level latency_ms
+  is this run's FP32 request latency;
+* workloads.served_capacity: the same controllers at rising rates (8 s of arrivals
+  each) until p99 exceeds one 20 Hz period (50 ms): the highest rate that keeps it,
+  per form;
+* cpu_baseline: the FP64 oracle on a bounded sample of the uneven batch.
+Inputs are resident in HBM before timing starts. Block penalty weights
+prism_default_block_weights(H), over-relaxation 1.8.
 
-Prints one JSON line. Extra fields: per-step p50/p99 latency, iteration
-statistics, the fixed-100-iteration throughput, a roofline object for the
-solve kernel (timed live with HIP events on the solve's stream) and the FP64
-oracle timed on the host cores on a bounded sample.
-
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16|fp16]
-                    [--alpha A] [--no-cpu-baseline] [--iters-cap C] [--workload mpc|long|uneven|serve|sigma|plan]
-
---workload long: 12 joints, N = 8192, H = 100 (same generator).
---workload serve: 32 controllers with the uneven requests' sizes issue Poisson requests at 20 Hz
-each for --duration seconds into the continuous-batching server (warm start by
-shift, HBM-budget admission); `value` is the served throughput and latency is
-arrival to completion.
---workload sigma: the single-joint diagnostic of Sec. III-C: 200,000 white-noise
-sequences (H = 15, dt = 0.1, sigma = --sigma, v0 = 0, |v| <= 1, |a| <= 2, |j| <= 4)
-projected with one joint; reports the projected spread and the FP64 feasibility.
---workload plan: one optimizer iteration (prism_plan_step) per step on the default
-batch shape: draw 2048 samples from N(nu, diag sigma^2) on the device, project them to
-residual <= 1e-3, score them (tracking cost), softmax weights, mean/variance update.
---workload uneven: 64 requests with H in {20, 50, 100}, N in {128, 512, 2048, 4096},
-6 or 12 joints and dt in {0.02, 0.05}, each with its own factor, projected in one
-prism_proj_solve_batch call per step (FP32 and BF16 both timed; `value` is the
---precision one).
+Other workloads (one line each, --workload): mpc, long, uneven, serve, sigma (the
+single-joint diagnostic of Sec. III-C), plan (one optimizer iteration around the
+projection), literal (the printed Bregman iteration).
 """
 
 from __future__ import annotations
@@ -48,6 +47,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "projected trajectories/sec at residual \u22641e-3; p50/p99 request latency"
+
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_F32_TFLOPS = 157.3
@@ -58,6 +59,16 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # FP64: dense matrix 78.6 TFLOP/s; vector FP64 issues at the same lane rate as FP32
 # (78.6 TFLOP/s counting an FMA as two), so PEAK_VALU_TOPS lane operations per second.
 PEAK_MFMA_F64_TFLOPS = 78.6
+
+FORMS = ("fp32", "bf16", "fp16")
+FORM_NAME = {"fp32": "fp32", "bf16": "bf16+10fp32", "fp16": "fp16+10fp32"}
+FORM_DTYPE = {"fp32": "f32", "bf16": "bf16+f32", "fp16": "f16+f32"}
+T_START = time.time()
+
+
+def progress(msg: str):
+    """One line per finished step on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.time() - T_START:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def valu_ops_per_col_iter(H: int) -> float:
@@ -91,25 +102,25 @@ def literal_valu_ops_per_col_pass(H: int) -> float:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=list(FORMS))
     ap.add_argument("--alpha", type=float, default=1.8)
     ap.add_argument("--weights", default="default", choices=["default", "unit"],
                     help="block penalty weights: prism_default_block_weights(H) or all ones")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--iters-cap", type=int, default=20000)
-    ap.add_argument("--fp32-tail", type=int, default=0)
+    ap.add_argument("--fp32-tail", type=int, default=10,
+                    help="reduced forms: FP32 iterations after convergence")
     ap.add_argument("--N", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time a fixed iteration count instead of the residual target")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the fixed-100-iteration section (for single-mode profiles)")
-    ap.add_argument("--cpu-sample", type=int, default=1536, help="samples (all joints) for the oracle")
-    ap.add_argument("--workload", default="mpc",
-                    choices=["mpc", "long", "uneven", "serve", "sigma", "plan", "literal"])
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="samples (all joints) for the oracle (uneven batch: this / 64 per request)")
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "mpc", "long", "uneven", "serve", "sigma", "plan", "literal"])
     ap.add_argument("--passes", type=int, default=20, help="literal: printed Bregman passes")
     ap.add_argument("--delta", type=float, default=1.0, help="literal: penalty delta")
     ap.add_argument("--sigma", type=float, default=1.0, help="sigma: sampling sigma")
@@ -121,8 +132,12 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: warm-state pool")
     ap.add_argument("--grid-share", type=int, default=75, help="serve: percent of workgroup "
                     "slots one launch may take")
-    ap.add_argument("--no-side", action="store_true", help="uneven/serve/sigma/plan: skip the "
-                    "second precision")
+    ap.add_argument("--sweep-seconds", type=float, default=8.0,
+                    help="all: seconds of arrivals per served-capacity point (0: skip)")
+    ap.add_argument("--sweep-rates", default="20,25,30,35,40,45,50,60,70,80,100",
+                    help="all: per-controller rates (Hz) of the served-capacity sweep")
+    ap.add_argument("--no-serve", action="store_true", help="all: skip the serving runs")
+    ap.add_argument("--no-side", action="store_true", help="one form only (--precision)")
     ap.add_argument("--cold", action="store_true", help="serve: no warm start (sample "
                     "counts alternate so no request matches its predecessor)")
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
@@ -164,49 +179,85 @@ def measured_traffic(key: str, sha: str = None):
                      t["write_kib_per_dispatch"] * t["write_factor"])
 
 
-def _oracle_threads():
+BLAS_ENV = ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")
+
+
+def _cpu_worker_init():
+    """Each worker process runs the oracle single-threaded (its products are small; BLAS
+    threads only contend on them): the spawned interpreter inherits BLAS_ENV = 1, read by
+    every BLAS library when it loads; the oracle is imported here, before any task."""
+    import oracle.admm  # noqa: F401
+
+
+def _cpu_oracle_task(t):
+    from oracle import admm
+    samples, H, dt, bounds, q0, v0, rho, alpha, cap, tol, ce, weights = t
+    t0 = time.perf_counter()
+    O = admm.solve_request(samples, H, dt, bounds, q0, v0, rho=rho, alpha=alpha, iters=cap,
+                           tol=tol, check_every=ce, weights=weights)
+    return samples.shape[0], int(O.iters.max()), time.perf_counter() - t0
+
+
+def cpu_oracle_pool(tasks, label):
+    """The FP64 oracle on the host cores: one single-threaded worker process per core
+    (at most 16, the GPU machine's CPU share), the tasks (requests or slices of one) spread
+    over them. Workers are started fresh (spawn) and never touch the GPU. Returns
+    (trajectories, wall seconds, workers, largest iteration count)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    saved = {k: os.environ.get(k) for k in BLAS_ENV}
+    os.environ.update({k: "1" for k in BLAS_ENV})
     try:
-        from threadpoolctl import threadpool_info
-        return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
-    except Exception:
-        return 1
+        ctx = mp.get_context("spawn")
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx,
+                                    initializer=_cpu_worker_init) as ex:
+            # the workers are up (interpreter and oracle imported) before the clock starts
+            list(ex.map(time.sleep, [0.0] * workers))
+            t0 = time.perf_counter()
+            n, itmax, done = 0, 0, 0
+            futs = [ex.submit(_cpu_oracle_task, t) for t in tasks]
+            for f in cf.as_completed(futs):
+                k, it, _ = f.result()
+                n += k
+                itmax = max(itmax, it)
+                done += 1
+                if done % 8 == 0 or done == len(futs):
+                    progress(f"{label}: {done}/{len(futs)} tasks, {time.perf_counter() - t0:.1f} s")
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return n, wall, workers, itmax
 
 
 def cpu_baseline(req, tol, check_every, cap, alpha, nsamp, weights):
-    """The FP64 oracle on the first nsamp samples (all joints), timed on the host."""
-    from oracle import admm
+    """The FP64 oracle on the first nsamp samples (all joints) of one request."""
     S = req.samples[:nsamp]
     chunk = 32
-    itmax = 0
-    t0 = time.perf_counter()
-    for c0 in range(0, S.shape[0], chunk):
-        O = admm.solve_request(S[c0:c0 + chunk], req.H, req.dt, req.bounds, req.q0, req.v0,
-                               rho=req.rho, alpha=alpha, iters=cap, tol=tol,
-                               check_every=check_every, weights=weights)
-        itmax = max(itmax, int(O.iters.max()))
-    dt = time.perf_counter() - t0
-    return {"value": S.shape[0] / dt, "unit": "trajectories/s", "cores": _oracle_threads(),
-            "kind": "oracle",
-            "sample": f"first {S.shape[0]} samples x {req.nj} joints of the benchmark batch "
-                      f"(oracle called on {chunk} samples at a time), FP64 NumPy oracle to "
-                      f"residual <= {tol:g} (check every {check_every}); {dt:.1f} s; max group "
-                      f"iterations {itmax}"}
+    tasks = [(S[c0:c0 + chunk], req.H, req.dt, req.bounds, req.q0, req.v0, req.rho, alpha, cap,
+              tol, check_every, weights) for c0 in range(0, S.shape[0], chunk)]
+    n, dt, workers, itmax = cpu_oracle_pool(tasks, "cpu baseline")
+    return {"value": n / dt, "unit": "trajectories/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {n} samples x {req.nj} joints of the benchmark batch, FP64 NumPy "
+                      f"oracle to residual <= {tol:g} (check every {check_every}), {chunk} samples "
+                      f"per task over {workers} single-threaded worker processes; {dt:.1f} s; "
+                      f"max iterations {itmax}"}
 
 
 def cpu_baseline_batch(reqs, tol, check_every, cap, alpha, per_req, weights_of):
-    """The FP64 oracle on the first per_req samples of every request, timed on the host."""
-    from oracle import admm
-    n = 0
-    t0 = time.perf_counter()
-    for r in reqs:
-        S = r.samples[:per_req]
-        admm.solve_request(S, r.H, r.dt, r.bounds, r.q0, r.v0, rho=r.rho, alpha=alpha, iters=cap,
-                           tol=tol, check_every=check_every, weights=weights_of(r))
-        n += S.shape[0]
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "trajectories/s", "cores": _oracle_threads(), "kind": "oracle",
+    """The FP64 oracle on the first per_req samples of every request."""
+    tasks = [(r.samples[:per_req], r.H, r.dt, r.bounds, r.q0, r.v0, r.rho, alpha, cap, tol,
+              check_every, weights_of(r)) for r in reqs]
+    n, dt, workers, itmax = cpu_oracle_pool(tasks, "cpu baseline")
+    return {"value": n / dt, "unit": "trajectories/s", "cores": workers, "kind": "oracle",
             "sample": f"first {per_req} samples of each of the {len(reqs)} requests ({n} "
-                      f"trajectories), FP64 NumPy oracle to residual <= {tol:g}; {dt:.1f} s"}
+                      f"trajectories), FP64 NumPy oracle to residual <= {tol:g}, one request per "
+                      f"task over {workers} single-threaded worker processes; {dt:.1f} s; max "
+                      f"iterations {itmax}"}
 
 
 def roofline(col_iters_by_H, kern_s, prec_is_f32):
@@ -248,41 +299,110 @@ def _timed(fn, steps, warmup, stream):
     return wall, np.array([s.elapsed_time(e) for s, e in ev])
 
 
-def run_batch(a):
-    """Uneven batch: 64 requests, one prism_proj_solve_batch call per step."""
-    import torch
-    import workloads as W
-    from paper_2608_25666_amd import Batch, Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
-    reqs = W.uneven_requests()
-    dev = torch.device("cuda:0")
-    handles = {}
-    for r in reqs:
-        key = (r.H, r.nj, r.dt)
-        if key not in handles:
-            handles[key] = Projector(r.H, r.nj, r.dt, r.bounds, r.rho,
-                                     weights=None if a.weights == "unit" else "default")
-    xs = [torch.from_numpy(r.samples).to(dev) for r in reqs]
-    outs = [torch.empty_like(x) for x in xs]
-    rps = [torch.empty((r.N, r.nj), dtype=torch.float32, device=dev) for r in reqs]
-    rds = [torch.empty_like(t) for t in rps]
-    its = [torch.empty((r.N, r.nj), dtype=torch.int32, device=dev) for r in reqs]
-    B = Batch()
-    stream = torch.cuda.current_stream()
+def _prec(name):
+    from paper_2608_25666_amd import PREC_BF16, PREC_FP16, PREC_FP32
+    return {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[name]
+
+
+def form_options(a, form, fixed=False):
+    from paper_2608_25666_amd import options
+    return options(precision=_prec(form), alpha=a.alpha, tol=0.0 if fixed else a.tol,
+                   check_every=a.check_every, fp32_tail=0 if form == "fp32" else a.fp32_tail)
+
+
+def _forms(a):
+    return (a.precision,) if a.no_side else tuple(
+        [a.precision] + [f for f in FORMS if f != a.precision])
+
+
+def _weights(a):
+    return None if a.weights == "unit" else "default"
+
+
+def measure_single(a, req, P, form, stream, bufs, traffic_key=None):
+    """One prism_proj_solve per step on a single request; HIP events on the solve's
+    stream give the per-launch times the roofline uses."""
+    x, out, rp, rd, it = bufs
     fixed = a.fixed_iters > 0
     n_it = a.fixed_iters if fixed else a.iters_cap
-    total_traj = sum(r.N for r in reqs)
+    opts = form_options(a, form, fixed)
+    wall, per = _timed(lambda: P.solve(x, req.q0, req.v0, n_it, opts=opts, out=out, r_primal=rp,
+                                       r_dual=rd, iters_out=it, stream=stream),
+                       a.steps, a.warmup, stream)
+    iters = it.cpu().numpy()
+    res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
+    ms = wall * 1e3 / a.steps
+    kern_s = float(per.mean()) * 1e-3
+    roof = roofline({req.H: float(iters.sum())}, kern_s, form == "fp32")
+    roof["traffic"] = measured_traffic(traffic_key) if traffic_key else None
+    roof["algorithmic_bytes"] = req.N * req.nj * (8 * req.H + 12)
+    roof["hbm_gbs"] = roof["algorithmic_bytes"] / kern_s / 1e9
+    progress(f"{req.N} x {req.nj} x H={req.H} {FORM_NAME[form]}: {ms:.3f} ms/step, "
+             f"{req.N / (ms * 1e-3) / 1e6:.3f}M traj/s, max iterations {int(iters.max())}")
+    return {"value": req.N / (ms * 1e-3), "ms_per_step": ms,
+            "latency_ms": {"p50": float(np.percentile(per, 50)),
+                           "p99": float(np.percentile(per, 99))},
+            "iterations": {"max": int(iters.max()), "mean": float(iters.mean()),
+                           "p50": float(np.median(iters)),
+                           "converged_frac": float(np.mean(res <= a.tol))},
+            "roofline": roof}
 
-    def measure(prec):
-        opts = options(precision=prec, alpha=a.alpha, tol=0.0 if fixed else a.tol,
-                       check_every=a.check_every, fp32_tail=a.fp32_tail)
-        items = [dict(proj=handles[(r.H, r.nj, r.dt)], samples=x, q0=r.q0, v0=r.v0, iters=n_it,
-                      out=o, r_primal=rp, r_dual=rd, iters_out=it)
-                 for r, x, o, rp, rd, it in zip(reqs, xs, outs, rps, rds, its)]
-        wall, per = _timed(lambda: B.solve(items, opts=opts, stream=stream), a.steps, a.warmup,
-                           stream)
+
+def run_single_workload(a, req, traffic_prefix):
+    """All forms of one single-solve workload (mpc or long horizon)."""
+    import torch
+    from paper_2608_25666_amd import Projector
+    dev = torch.device("cuda:0")
+    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho, weights=_weights(a))
+    x = torch.from_numpy(req.samples).to(dev)
+    bufs = (x, torch.empty_like(x), torch.empty((req.N, req.nj), dtype=torch.float32, device=dev),
+            torch.empty((req.N, req.nj), dtype=torch.float32, device=dev),
+            torch.empty((req.N, req.nj), dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+    out = {}
+    for f in _forms(a):
+        key = f"{traffic_prefix}_{f}_residual" if a.fixed_iters == 0 else None
+        out[FORM_NAME[f]] = measure_single(a, req, P, f, stream, bufs, key)
+    P.close()
+    return out, P.weights
+
+
+class UnevenBatch:
+    """The 64-request uneven batch, resident on the device, with one handle per shape."""
+
+    def __init__(self, a):
+        import torch
+        import workloads as W
+        from paper_2608_25666_amd import Batch, Projector
+        self.reqs = W.uneven_requests()
+        dev = torch.device("cuda:0")
+        self.handles = {}
+        for r in self.reqs:
+            key = (r.H, r.nj, r.dt)
+            if key not in self.handles:
+                self.handles[key] = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights=_weights(a))
+        self.xs = [torch.from_numpy(r.samples).to(dev) for r in self.reqs]
+        self.outs = [torch.empty_like(x) for x in self.xs]
+        self.rps = [torch.empty((r.N, r.nj), dtype=torch.float32, device=dev) for r in self.reqs]
+        self.rds = [torch.empty_like(t) for t in self.rps]
+        self.its = [torch.empty((r.N, r.nj), dtype=torch.int32, device=dev) for r in self.reqs]
+        self.B = Batch()
+        self.total = sum(r.N for r in self.reqs)
+        progress(f"uneven batch resident: {len(self.reqs)} requests, {self.total} trajectories")
+
+    def measure(self, a, form, stream):
+        fixed = a.fixed_iters > 0
+        n_it = a.fixed_iters if fixed else a.iters_cap
+        opts = form_options(a, form, fixed)
+        items = [dict(proj=self.handles[(r.H, r.nj, r.dt)], samples=x, q0=r.q0, v0=r.v0,
+                      iters=n_it, out=o, r_primal=rp, r_dual=rd, iters_out=it)
+                 for r, x, o, rp, rd, it in zip(self.reqs, self.xs, self.outs, self.rps,
+                                                self.rds, self.its)]
+        wall, per = _timed(lambda: self.B.solve(items, opts=opts, stream=stream), a.steps,
+                           a.warmup, stream)
         col_iters = {}
-        worst, conv, itmax, itsum, ncol = 0.0, 0, 0, 0.0, 0
-        for r, rp, rd, it in zip(reqs, rps, rds, its):
+        conv, itmax, itsum, ncol = 0, 0, 0.0, 0
+        for r, rp, rd, it in zip(self.reqs, self.rps, self.rds, self.its):
             i = it.cpu().numpy()
             res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
             col_iters[r.H] = col_iters.get(r.H, 0.0) + float(i.sum())
@@ -291,67 +411,70 @@ def run_batch(a):
             itmax = max(itmax, int(i.max()))
             itsum += float(i.sum())
         ms = wall * 1e3 / a.steps
-        roof = roofline(col_iters, float(per.mean()) * 1e-3, prec == PREC_FP32)
-        return {"value": total_traj / (ms * 1e-3), "ms_per_step": ms,
+        kern_s = float(per.mean()) * 1e-3
+        roof = roofline(col_iters, kern_s, form == "fp32")
+        roof["traffic"] = (measured_traffic(f"uneven_64_requests_{form}_residual")
+                           if not fixed else None)
+        roof["algorithmic_bytes"] = sum(r.N * r.nj * (8 * r.H + 12) for r in self.reqs)
+        roof["hbm_gbs"] = roof["algorithmic_bytes"] / kern_s / 1e9
+        progress(f"uneven batch {FORM_NAME[form]}: {ms:.3f} ms/step, "
+                 f"{self.total / (ms * 1e-3) / 1e6:.3f}M traj/s, max iterations {itmax}")
+        return {"value": self.total / (ms * 1e-3), "ms_per_step": ms,
                 "latency_ms": {"p50": float(np.percentile(per, 50)),
                                "p99": float(np.percentile(per, 99))},
                 "iterations": {"max": itmax, "mean": itsum / ncol, "converged_frac": conv / ncol},
                 "roofline": roof}
 
-    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
-    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
-    m = measure(main_prec)
-    o = measure(other)
-    shapes = sorted({(r.H, r.nj, r.dt) for r in reqs})
-    line = {
-        "metric": ("projected trajectories/sec at residual <=1e-3" if not fixed else
-                   f"projected trajectories/sec at {a.fixed_iters} iterations"),
-        "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if main_prec == PREC_FP32 else ("bf16+f32" if main_prec == PREC_BF16
-                                                         else "f16+f32"),
-        "data": "synthetic",
-        "config": {"workload": "uneven batch in one persistent launch: 64 requests, H in "
-                               "{20,50,100}, N in {128,512,2048,4096}, 6 or 12 joints, dt in "
-                               "{0.02,0.05}, own factor each, smooth 3-sinusoid + N(0,0.5^2) "
-                               "samples, residual <= 1e-3",
-                   "requests": len(reqs), "trajectories": total_traj,
-                   "distinct_factors": len(shapes), "alpha": a.alpha, "precision": a.precision,
-                   "tol": a.tol, "check_every": a.check_every, "iters_cap": a.iters_cap},
-        "latency_ms": m["latency_ms"], "iterations": m["iterations"], "roofline": m["roofline"],
-        "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o},
-    }
-    if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_batch(
-            reqs, a.tol, a.check_every, a.iters_cap, a.alpha, max(1, a.cpu_sample // 64),
-            lambda r: handles[(r.H, r.nj, r.dt)].weights)
-    print(json.dumps(line), flush=True)
+    def config(self, a):
+        shapes = sorted({(r.H, r.nj, r.dt) for r in self.reqs})
+        return {"workload": "uneven batch in one persistent launch: 64 requests, H in "
+                            "{20,50,100}, N in {128,512,2048,4096}, 6 or 12 joints, dt in "
+                            "{0.02,0.05}, own factor each, smooth 3-sinusoid + N(0,0.5^2) "
+                            f"samples, residual <= {a.tol:g}",
+                "requests": len(self.reqs), "trajectories": self.total,
+                "distinct_factors": len(shapes), "alpha": a.alpha,
+                "block_weights": "prism_default_block_weights(H)" if a.weights == "default"
+                                 else "unit", "tol": a.tol, "check_every": a.check_every,
+                "iters_cap": a.iters_cap, "reduced_forms_fp32_tail": a.fp32_tail}
 
 
-def run_serve(a):
-    """Serving: Poisson arrivals from many controllers into prism_server."""
+class ServingSetup:
+    """Controllers of the serving workload, their handles and resident samples."""
+
+    def __init__(self, a, n_sets=8):
+        import torch
+        from workloads import recipes as WC
+        from paper_2608_25666_amd import Projector
+        self.ctrls = WC.serving_controllers(n_controllers=a.controllers, rate_hz=a.rate,
+                                            duration_s=a.duration)
+        dev = torch.device("cuda:0")
+        self.n_sets = n_sets
+        self.handles = {}
+        for c in self.ctrls:
+            key = (c.H, c.nj, c.dt)
+            if key not in self.handles:
+                self.handles[key] = Projector(c.H, c.nj, c.dt, WC.UR5E_BIMANUAL_BOUNDS(c.nj), 1.0,
+                                              weights=_weights(a))
+        # samples of steps 0..n_sets-1 per controller, resident before the run (request k
+        # uses step k mod n_sets)
+        self.sets = [[torch.from_numpy(WC.controller_samples(c, k)).to(dev) for k in range(n_sets)]
+                     for c in self.ctrls]
+        if a.cold:   # every other request one sample short: never the predecessor's count
+            self.sets = [[s if k % 2 == 0 else s[:-1] for k, s in enumerate(ss)]
+                         for ss in self.sets]
+        self.outs = [[torch.empty_like(self.sets[ci][0]), torch.empty_like(self.sets[ci][0])]
+                     for ci in range(len(self.ctrls))]
+        progress(f"serving samples resident: {len(self.ctrls)} controllers x {n_sets} steps")
+
+
+def serve_run(a, S0, form, arrivals_per_ctrl, duration, label):
+    """Poisson arrivals into prism_server; latency is arrival to completion."""
+    import gc
     import torch
-    from workloads import recipes as WC
-    from paper_2608_25666_amd import Projector, Server, now_ns, options
-    from paper_2608_25666_amd import PREC_FP32, PREC_BF16, PREC_FP16
-    ctrls = WC.serving_controllers(n_controllers=a.controllers, rate_hz=a.rate,
-                                   duration_s=a.duration)
+    from paper_2608_25666_amd import Server, now_ns
+    ctrls, sets, outs, n_sets = S0.ctrls, S0.sets, S0.outs, S0.n_sets
     dev = torch.device("cuda:0")
-    n_sets = 8
-    handles = {}
-    for c in ctrls:
-        key = (c.H, c.nj, c.dt)
-        if key not in handles:
-            handles[key] = Projector(c.H, c.nj, c.dt, WC.UR5E_BIMANUAL_BOUNDS(c.nj), 1.0,
-                                     weights=None if a.weights == "unit" else "default")
-    # samples of steps 0..n_sets-1 per controller, resident before the run (request k uses
-    # step k mod n_sets)
-    sets = [[torch.from_numpy(WC.controller_samples(c, k)).to(dev) for k in range(n_sets)]
-            for c in ctrls]
-    if a.cold:       # every other request one sample short: never the predecessor's count
-        sets = [[s if k % 2 == 0 else s[:-1] for k, s in enumerate(ss)] for ss in sets]
-    arrivals = sorted((float(t), ci) for ci, c in enumerate(ctrls) for t in c.arrivals)
+    arrivals = sorted((float(t), ci) for ci, ts in enumerate(arrivals_per_ctrl) for t in ts)
     n_req = len(arrivals)
     step_of = []
     cnt = [0] * len(ctrls)
@@ -364,111 +487,242 @@ def run_serve(a):
     it_all = torch.zeros(int(offs[-1]), dtype=torch.int32, device=dev)
     rp_all = torch.zeros(int(offs[-1]), dtype=torch.float32, device=dev)
     rd_all = torch.zeros_like(rp_all)
-    outs = [[torch.empty_like(sets[ci][0]), torch.empty_like(sets[ci][0])] for ci in range(len(ctrls))]
+    opts = form_options(a, form)
+    S = Server(budget=int(a.budget_gb * (1 << 30)), opts=opts, max_inflight=a.max_inflight,
+               max_batch=a.max_batch, grid_share=a.grid_share)
+    ids = [S.add_controller(S0.handles[(c.H, c.nj, c.dt)], c.N) for c in ctrls]
+    # warm-up (untimed): every controller's step 0, so kernels are loaded and each
+    # controller holds a warm state when the arrival clock starts
+    warm = [S.submit(ids[ci], sets[ci][0], c.q0, c.v0, a.iters_cap, outs[ci][1])
+            for ci, c in enumerate(ctrls)]
+    for t in warm:
+        S.wait(t, 120000)
+        S.release(t)
+    torch.cuda.synchronize()
+    tickets = []
+    lags = np.zeros(len(arrivals))
+    gc.collect()
+    gc.disable()          # a collection pass over the live tickets stalls the submitter
+    t0 = now_ns() + 20_000_000
+    late = 0
+    next_report = 5.0
+    for i, ((t, ci), k) in enumerate(zip(arrivals, step_of)):
+        if t >= next_report:
+            print(f"[{label}] {t:.0f} s of arrivals, {i} requests submitted", file=sys.stderr,
+                  flush=True)
+            next_report += 5.0
+        due = t0 + int(t * 1e9)
+        while True:
+            d = due - now_ns()
+            if d <= 0:
+                break
+            if d > 2_000_000:
+                time.sleep((d - 1_000_000) / 1e9)
+        lags[i] = (now_ns() - due) / 1e6
+        late = max(late, now_ns() - due)
+        x = sets[ci][(k + 1) % n_sets]
+        o = outs[ci][k % 2][:x.shape[0]]
+        sl = slice(int(offs[i]), int(offs[i + 1]))
+        c = ctrls[ci]
+        tickets.append(S.submit(ids[ci], x, c.q0, c.v0, a.iters_cap, o,
+                                r_primal=rp_all[sl].view(x.shape[0], c.nj),
+                                r_dual=rd_all[sl].view(x.shape[0], c.nj),
+                                iters_out=it_all[sl].view(x.shape[0], c.nj)))
+    infos = [S.wait(t, 120000) for t in tickets]
+    gc.enable()
+    torch.cuda.synchronize()
+    stats = S.stats()
+    for t in tickets:
+        S.release(t)
+    S.close()
+    lat = np.array([(inf["t_done_ns"] - (t0 + int(t * 1e9))) / 1e6
+                    for inf, (t, _) in zip(infos, arrivals)])
+    t_end = max(inf["t_done_ns"] for inf in infos)
+    span = (t_end - t0) / 1e9
+    traj = sum(sets[ci][(k + 1) % n_sets].shape[0] for (_, ci), k in zip(arrivals, step_of))
+    it_np = it_all.cpu().numpy()
+    res = np.maximum(rp_all.cpu().numpy(), rd_all.cpu().numpy())
+    col_iters = {}
+    for i, ((_, ci), k) in enumerate(zip(arrivals, step_of)):
+        H = ctrls[ci].H
+        col_iters[H] = col_iters.get(H, 0.0) + float(it_np[offs[i]:offs[i + 1]].sum())
+    warm_frac = float(np.mean([inf["warm"] for inf in infos]))
+    offered = traj / duration
+    progress(f"{label}: {traj / span / 1e6:.3f}M traj/s served, request latency p50 "
+             f"{np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+    return {"value": traj / span, "offered_trajectories_per_s": offered,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+            "requests": n_req, "trajectories": int(traj), "span_s": span,
+            "warm_frac": warm_frac, "max_submit_lag_ms": late / 1e6,
+            "submit_lag_ms": {"p50": float(np.percentile(lags, 50)),
+                              "p99": float(np.percentile(lags, 99))},
+            "iterations": {"mean": float(it_np.mean()), "max": int(it_np.max()),
+                           "converged_frac": float(np.mean(res <= a.tol))},
+            "mean_batch": float(np.mean([inf["batch_size"] for inf in infos])),
+            "launches": stats["launches"], "evictions": stats["evictions"],
+            "max_concurrent_launches": stats["max_concurrent_launches"],
+            "gpu_busy_work": roofline(col_iters, span, form == "fp32")}
 
-    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
 
-    def one_run(prec):
-        opts = options(precision=prec, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
-                       fp32_tail=a.fp32_tail if prec == PREC_FP32 else max(a.fp32_tail, 10))
-        S = Server(budget=int(a.budget_gb * (1 << 30)), opts=opts, max_inflight=a.max_inflight,
-                   max_batch=a.max_batch, grid_share=a.grid_share)
-        ids = [S.add_controller(handles[(c.H, c.nj, c.dt)], c.N) for c in ctrls]
-        # warm-up (untimed): every controller's step 0, so kernels are loaded and each
-        # controller holds a warm state when the arrival clock starts
-        warm = [S.submit(ids[ci], sets[ci][0], c.q0, c.v0, a.iters_cap, outs[ci][1])
-                for ci, c in enumerate(ctrls)]
-        for t in warm:
-            S.wait(t, 120000)
-            S.release(t)
-        torch.cuda.synchronize()
-        tickets = []
-        lags = np.zeros(len(arrivals))
-        import gc
-        gc.collect()
-        gc.disable()          # a collection pass over the live tickets stalls the submitter
-        t0 = now_ns() + 20_000_000
-        late = 0
-        next_report = 5.0
-        for i, ((t, ci), k) in enumerate(zip(arrivals, step_of)):
-            if t >= next_report:
-                print(f"[serve {a.precision if prec == main_prec else 'other'}] {t:.0f} s of "
-                      f"arrivals, {i} requests submitted", file=sys.stderr, flush=True)
-                next_report += 5.0
-            due = t0 + int(t * 1e9)
-            while True:
-                d = due - now_ns()
-                if d <= 0:
-                    break
-                if d > 2_000_000:
-                    time.sleep((d - 1_000_000) / 1e9)
-            lags[i] = (now_ns() - due) / 1e6
-            late = max(late, now_ns() - due)
-            x = sets[ci][(k + 1) % n_sets]
-            o = outs[ci][k % 2][:x.shape[0]]
-            sl = slice(int(offs[i]), int(offs[i + 1]))
-            c = ctrls[ci]
-            tickets.append(S.submit(ids[ci], x, c.q0, c.v0, a.iters_cap, o,
-                                    r_primal=rp_all[sl].view(x.shape[0], c.nj),
-                                    r_dual=rd_all[sl].view(x.shape[0], c.nj),
-                                    iters_out=it_all[sl].view(x.shape[0], c.nj)))
-        infos = [S.wait(t, 120000) for t in tickets]
-        gc.enable()
-        torch.cuda.synchronize()
-        stats = S.stats()
-        for t in tickets:
-            S.release(t)
-        S.close()
-        lat = np.array([(inf["t_done_ns"] - (t0 + int(t * 1e9))) / 1e6
-                        for inf, (t, _) in zip(infos, arrivals)])
-        t_end = max(inf["t_done_ns"] for inf in infos)
-        span = (t_end - t0) / 1e9
-        traj = sum(sets[ci][(k + 1) % n_sets].shape[0] for (_, ci), k in zip(arrivals, step_of))
-        it_np = it_all.cpu().numpy()
-        res = np.maximum(rp_all.cpu().numpy(), rd_all.cpu().numpy())
-        col_iters = {}
-        for i, ((_, ci), k) in enumerate(zip(arrivals, step_of)):
-            H = ctrls[ci].H
-            col_iters[H] = col_iters.get(H, 0.0) + float(it_np[offs[i]:offs[i + 1]].sum())
-        warm = float(np.mean([inf["warm"] for inf in infos]))
-        return {"value": traj / span, "latency_ms": {"p50": float(np.percentile(lat, 50)),
-                                                     "p99": float(np.percentile(lat, 99)),
-                                                     "max": float(lat.max())},
-                "requests": n_req, "trajectories": int(traj), "span_s": span,
-                "warm_frac": warm, "max_submit_lag_ms": late / 1e6,
-                "submit_lag_ms": {"p50": float(np.percentile(lags, 50)),
-                                  "p99": float(np.percentile(lags, 99))},
-                "iterations": {"mean": float(it_np.mean()), "max": int(it_np.max()),
-                               "converged_frac": float(np.mean(res <= a.tol))},
-                "mean_batch": float(np.mean([inf["batch_size"] for inf in infos])),
-                "launches": stats["launches"], "evictions": stats["evictions"],
-                "max_concurrent_launches": stats["max_concurrent_launches"],
-                "gpu_busy_work": roofline(col_iters, span, prec == PREC_FP32)}
+def served_capacity(a, S0, forms):
+    """Highest per-controller rate whose p99 request latency stays within one 20 Hz
+    period (50 ms), per form: rising rates, a_sweep_seconds of arrivals each; a form's
+    sweep stops at its first rate over the limit."""
+    import workloads as W
+    rates = [float(r) for r in a.sweep_rates.split(",") if r.strip()]
+    out = {}
+    for f in forms:
+        pts, best = [], None
+        for rate in rates:
+            arr = W.poisson_arrivals(len(S0.ctrls), rate, a.sweep_seconds)
+            m = serve_run(a, S0, f, arr, a.sweep_seconds, f"capacity {FORM_NAME[f]} {rate:g} Hz")
+            pts.append({"rate_hz": rate, "trajectories_per_s": m["value"],
+                        "offered_trajectories_per_s": m["offered_trajectories_per_s"],
+                        "p50_ms": m["latency_ms"]["p50"], "p99_ms": m["latency_ms"]["p99"],
+                        "converged_frac": m["iterations"]["converged_frac"]})
+            print(f"[capacity {FORM_NAME[f]}] {rate:g} Hz: p99 {m['latency_ms']['p99']:.1f} ms, "
+                  f"{m['value'] / 1e6:.2f}M traj/s", file=sys.stderr, flush=True)
+            if m["latency_ms"]["p99"] > 50.0:
+                break
+            best = pts[-1]
+        out[FORM_NAME[f]] = {"highest_rate_hz_p99_le_50ms": None if best is None else best["rate_hz"],
+                             "trajectories_per_s": None if best is None else best["trajectories_per_s"],
+                             "p99_ms": None if best is None else best["p99_ms"], "sweep": pts}
+    return out
 
-    main_prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
-    other = PREC_BF16 if main_prec == PREC_FP32 else PREC_FP32
-    m = one_run(main_prec)
-    o = None if a.no_side else one_run(other)
+
+def run_all(a):
+    """The default line: the uneven batch as `value`, the other workloads beside it."""
+    import torch
+    import workloads as W
+    stream = torch.cuda.current_stream()
+    forms = _forms(a)
+    ub = UnevenBatch(a)
+    res = {f: ub.measure(a, f, stream) for f in forms}
+    m = res[a.precision]
     line = {
-        "metric": "projected trajectories/sec at residual <=1e-3; p50/p99 request latency",
-        "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": m["requests"],
-        "warmup": 0, "ms_per_step": m["span_s"] * 1e3 / max(1, m["requests"]),
+        "metric": METRIC, "value": m["value"], "unit": "trajectories/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": m["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if main_prec == PREC_FP32 else ("bf16+f32" if main_prec == PREC_BF16
-                                                         else "f16+f32"),
-        "data": "synthetic",
-        "config": {"workload": f"serving: {len(ctrls)} controllers (uneven-request sizes), Poisson "
-                               f"{a.rate:g} Hz each for {a.duration:g} s, warm start by shift, "
-                               f"HBM-budget admission, residual <= {a.tol:g}",
-                   "controllers": len(ctrls), "rate_hz": a.rate, "duration_s": a.duration,
-                   "budget_gb": a.budget_gb, "max_inflight": a.max_inflight,
-                   "max_batch": a.max_batch, "grid_share": a.grid_share, "alpha": a.alpha,
-                   "precision": a.precision,
-                   "cold": a.cold},
-        "latency_ms": m["latency_ms"], "serving": {k: v for k, v in m.items()
-                                                   if k not in ("value", "latency_ms")},
-        "side_by_side": {("bf16" if other == PREC_BF16 else "fp32"): o},
+        "dtype": FORM_DTYPE[a.precision], "data": "synthetic", "config": ub.config(a),
+        "launch_latency_ms": m["latency_ms"], "iterations": m["iterations"],
+        "roofline": m["roofline"],
+        "side_by_side": {FORM_NAME[f]: res[f] for f in forms if f != a.precision},
     }
+    wl = {}
+    long_req = W.long_horizon_batch()
+    wl["long_horizon"], w_long = run_single_workload(a, long_req, "long_N8192_H100_J12")
+    wl["long_horizon"]["config"] = {
+        "workload": "single solve: 8192 samples x 12 joints, H=100, dt=0.02, smooth 3-sinusoid "
+                    f"+ N(0,0.5^2) samples, residual <= {a.tol:g}", "block_weights": w_long}
+    mpc_req = W.mpc_batch(N=a.N)
+    wl["mpc"], w_mpc = run_single_workload(a, mpc_req, f"mpc_N{a.N}_H50_J12")
+    wl["mpc"]["config"] = {
+        "workload": f"single solve: {a.N} samples x 12 joints, H=50, dt=0.02, smooth "
+                    f"3-sinusoid + N(0,0.5^2) samples, residual <= {a.tol:g}",
+        "block_weights": w_mpc}
+    if not a.no_serve:
+        S0 = ServingSetup(a)
+        sforms = [f for f in ("fp32", "bf16") if f in forms] or [a.precision]
+        serving = {}
+        for f in sforms:
+            arr = [c.arrivals for c in S0.ctrls]
+            serving[FORM_NAME[f]] = serve_run(a, S0, f, arr, a.duration, f"serve {FORM_NAME[f]}")
+        serving["config"] = {"workload": f"serving: {len(S0.ctrls)} controllers (uneven-request "
+                                         f"sizes), Poisson {a.rate:g} Hz each for "
+                                         f"{a.duration:g} s, warm start by shift, HBM-budget "
+                                         f"admission, residual <= {a.tol:g}",
+                             "budget_gb": a.budget_gb, "max_inflight": a.max_inflight,
+                             "max_batch": a.max_batch, "grid_share": a.grid_share}
+        wl["serving"] = serving
+        first = serving[FORM_NAME[sforms[0]]]
+        line["latency_ms"] = {"p50": first["latency_ms"]["p50"], "p99": first["latency_ms"]["p99"],
+                              "source": f"serving run, {FORM_NAME[sforms[0]]}, request arrival "
+                                        "to completion"}
+        if a.sweep_seconds > 0:
+            wl["served_capacity"] = served_capacity(a, S0, sforms)
+    line["workloads"] = wl
+    if not a.no_cpu_baseline:
+        progress("cpu baseline: the FP64 oracle on a sample of the uneven batch")
+        line["cpu_baseline"] = cpu_baseline_batch(
+            ub.reqs, a.tol, a.check_every, a.iters_cap, a.alpha, max(1, a.cpu_sample // 64),
+            lambda r: ub.handles[(r.H, r.nj, r.dt)].weights)
+        progress(f"cpu baseline: {line['cpu_baseline']['value']:.1f} traj/s")
+    print(json.dumps(line), flush=True)
+
+
+def run_uneven(a):
+    import torch
+    stream = torch.cuda.current_stream()
+    ub = UnevenBatch(a)
+    forms = _forms(a)
+    res = {f: ub.measure(a, f, stream) for f in forms}
+    m = res[a.precision]
+    line = {"metric": METRIC, "value": m["value"], "unit": "trajectories/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": m["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": FORM_DTYPE[a.precision], "data": "synthetic", "config": ub.config(a),
+            "launch_latency_ms": m["latency_ms"], "iterations": m["iterations"],
+            "roofline": m["roofline"],
+            "side_by_side": {FORM_NAME[f]: res[f] for f in forms if f != a.precision}}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(
+            ub.reqs, a.tol, a.check_every, a.iters_cap, a.alpha, max(1, a.cpu_sample // 64),
+            lambda r: ub.handles[(r.H, r.nj, r.dt)].weights)
+    print(json.dumps(line), flush=True)
+
+
+def run_single(a):
+    import workloads as W
+    req = W.long_horizon_batch() if a.workload == "long" else W.mpc_batch(N=a.N)
+    prefix = "long_N8192_H100_J12" if a.workload == "long" else f"mpc_N{a.N}_H50_J12"
+    res, w = run_single_workload(a, req, prefix)
+    m = res[FORM_NAME[a.precision]]
+    line = {"metric": METRIC if a.fixed_iters == 0 else
+            f"projected trajectories/sec at {a.fixed_iters} iterations",
+            "value": m["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": FORM_DTYPE[a.precision],
+            "data": "synthetic",
+            "config": {"workload": f"single solve: {req.N} samples x {req.nj} joints, H={req.H}, "
+                                   f"dt={req.dt}, smooth 3-sinusoid + N(0,0.5^2) samples, "
+                                   + (f"residual <= {a.tol:g}" if a.fixed_iters == 0 else
+                                      f"{a.fixed_iters} iterations"),
+                       "alpha": a.alpha, "block_weights": w, "check_every": a.check_every,
+                       "iters_cap": a.iters_cap},
+            "launch_latency_ms": m["latency_ms"], "iterations": m["iterations"],
+            "roofline": m["roofline"],
+            "side_by_side": {k: v for k, v in res.items() if k != FORM_NAME[a.precision]}}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(req, a.tol, a.check_every, a.iters_cap, a.alpha,
+                                            a.cpu_sample, w)
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(a):
+    S0 = ServingSetup(a)
+    forms = _forms(a)
+    res = {}
+    for f in forms[:2]:
+        res[FORM_NAME[f]] = serve_run(a, S0, f, [c.arrivals for c in S0.ctrls], a.duration,
+                                      f"serve {FORM_NAME[f]}")
+    m = res[FORM_NAME[a.precision]]
+    line = {"metric": METRIC, "value": m["value"], "unit": "trajectories/s", "n_gpus": 1,
+            "steps": m["requests"], "warmup": 0,
+            "ms_per_step": m["span_s"] * 1e3 / max(1, m["requests"]),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": FORM_DTYPE[a.precision], "data": "synthetic",
+            "config": {"workload": f"serving: {len(S0.ctrls)} controllers (uneven-request sizes), "
+                                   f"Poisson {a.rate:g} Hz each for {a.duration:g} s, warm start "
+                                   f"by shift, HBM-budget admission, residual <= {a.tol:g}",
+                       "controllers": len(S0.ctrls), "rate_hz": a.rate, "duration_s": a.duration,
+                       "budget_gb": a.budget_gb, "max_inflight": a.max_inflight,
+                       "max_batch": a.max_batch, "grid_share": a.grid_share, "alpha": a.alpha,
+                       "cold": a.cold},
+            "latency_ms": m["latency_ms"],
+            "serving": {k: v for k, v in m.items() if k not in ("value", "latency_ms")},
+            "side_by_side": {k: v for k, v in res.items() if k != FORM_NAME[a.precision]}}
     print(json.dumps(line), flush=True)
 
 
@@ -656,8 +910,13 @@ def run_literal(a):
                                problem.joint_limits(req.bounds, j), float(req.q0[j]),
                                float(req.v0[j]), delta=a.delta, iters=a.passes)
         dt_cpu = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+            cores = int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+        except Exception:
+            cores = 1
         line["cpu_baseline"] = {"value": N / dt_cpu, "unit": "trajectories/s",
-                                "cores": _oracle_threads(), "kind": "oracle",
+                                "cores": cores, "kind": "oracle",
                                 "sample": f"the whole batch ({N} samples x {nj} joints), "
                                           f"oracle literal_joint, {dt_cpu:.1f} s"}
     print(json.dumps(line), flush=True)
@@ -671,9 +930,9 @@ def main():
                           "shards by samples or requests across GPUs without communication; "
                           "run with --gpus 1"}))
         sys.exit(2)
+    progress(f"workload {a.workload}: importing torch")
     import torch
-    import workloads as W
-    from paper_2608_25666_amd import Projector, options, PREC_FP32, PREC_BF16, PREC_FP16
+    progress(f"torch {torch.__version__}, device {torch.cuda.get_device_name(0)}")
 
     if a.copy_calibrate_mb > 0:
         nbytes = a.copy_calibrate_mb << 20
@@ -683,152 +942,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.workload == "uneven":
-        return run_batch(a)
-    if a.workload == "serve":
-        return run_serve(a)
-    if a.workload == "sigma":
-        return run_sigma(a)
-    if a.workload == "plan":
-        return run_plan(a)
-    if a.workload == "literal":
-        return run_literal(a)
-    prec = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp16": PREC_FP16}[a.precision]
-    req = W.long_horizon_batch() if a.workload == "long" else W.mpc_batch(N=a.N)
-    dev = torch.device("cuda:0")
-    P = Projector(req.H, req.nj, req.dt, req.bounds, req.rho,
-                  weights=None if a.weights == "unit" else "default")
-    x = torch.from_numpy(req.samples).to(dev)
-    out = torch.empty_like(x)
-    rp = torch.empty((req.N, req.nj), dtype=torch.float32, device=dev)
-    rd = torch.empty_like(rp)
-    it = torch.empty((req.N, req.nj), dtype=torch.int32, device=dev)
-    fixed = a.fixed_iters > 0
-    opts = options(precision=prec, alpha=a.alpha, tol=0.0 if fixed else a.tol,
-                   check_every=a.check_every, fp32_tail=a.fp32_tail)
-    n_it = a.fixed_iters if fixed else a.iters_cap
-    stream = torch.cuda.current_stream()
-
-    def step():
-        P.solve(x, req.q0, req.v0, n_it, opts=opts, out=out, r_primal=rp, r_dual=rd,
-                iters_out=it, stream=stream)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
-        step()
-        e.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = np.array([s.elapsed_time(e) for s, e in ev])            # ms, solve launch on its stream
-    ms_step = wall * 1e3 / a.steps
-    iters = it.cpu().numpy()
-    res = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
-    converged = float(np.mean(res <= a.tol))
-
-    # fixed-count throughput (100 iterations)
-    fixed_ms = float("nan")
-    if not a.no_extras:
-        fopts = options(precision=prec, alpha=a.alpha, fp32_tail=a.fp32_tail)
-        for _ in range(2):
-            P.solve(x, req.q0, req.v0, 100, opts=fopts, out=out, r_primal=rp, r_dual=rd,
-                    stream=stream)
-        torch.cuda.synchronize()
-        fe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(10)]
-        for s, e in fe:
-            s.record(stream)
-            P.solve(x, req.q0, req.v0, 100, opts=fopts, out=out, r_primal=rp, r_dual=rd,
-                    stream=stream)
-            e.record(stream)
-        torch.cuda.synchronize()
-        fixed_ms = float(np.mean([s.elapsed_time(e) for s, e in fe]))
-
-    # roofline of the solve kernel over the timed region
-    H = req.H
-    col_iters = float(iters.sum())
-    valu = valu_ops_per_col_iter(H) * col_iters
-    mflop = mfma_flops_per_col_iter(H) * col_iters
-    kern_s = float(per.mean()) * 1e-3
-    t_valu = valu / (PEAK_VALU_TOPS * 1e12)
-    peak_mfma = PEAK_MFMA_F32_TFLOPS if prec == PREC_FP32 else PEAK_MFMA_B16_TFLOPS
-    t_mfma = mflop / (peak_mfma * 1e12)
-    if t_valu >= t_mfma:
-        ach = valu / kern_s / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_VALU_TOPS}
-    else:
-        ach = mflop / kern_s / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": peak_mfma, "unit": "TFLOP/s",
-                "frac": ach / peak_mfma}
-    roof["traffic"] = None
-    if a.workload == "mpc" and req.N == 2048 and prec == PREC_FP32 and not fixed:
-        roof["traffic"] = measured_traffic("mpc_N2048_H50_J12_fp32_residual")
-    roof["algorithmic_bytes"] = req.N * req.nj * H * 8 + req.N * req.nj * 12
-    roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
-    roof["hbm_gbs"] = roof["algorithmic_bytes"] / kern_s / 1e9
-    fixed_cols = req.N * req.nj * 100
-    fixed_valu = valu_ops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
-    fixed_mfma = mfma_flops_per_col_iter(H) * fixed_cols / (fixed_ms * 1e-3) / 1e12
-
-    line = {
-        "metric": ("projected trajectories/sec at residual <=1e-3" if not fixed else
-                   f"projected trajectories/sec at {a.fixed_iters} iterations"),
-        "value": req.N / (ms_step * 1e-3),
-        "unit": "trajectories/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == PREC_FP32 else ("bf16+f32" if prec == PREC_BF16 else "f16+f32"),
-        "data": "synthetic",
-        "config": {"workload": f"projection QP, 12 joints, N={req.N}, H={H}, dt={req.dt}, rho=1, "
-                               "smooth 3-sinusoid + N(0,0.5^2) samples, residual <= 1e-3",
-                   "N": req.N, "H": H, "joints": req.nj, "dt": req.dt, "rho": req.rho,
-                   "alpha": a.alpha, "block_weights": P.weights or (1.0, 1.0, 1.0, 1.0),
-                   "precision": a.precision, "tol": a.tol,
-                   "check_every": a.check_every, "iters_cap": a.iters_cap},
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
-        "iterations": {"max": int(iters.max()), "mean": float(iters.mean()),
-                       "p50": float(np.median(iters)), "converged_frac": converged},
-        "fixed_100_iters": {"ms": fixed_ms, "trajectories_per_s": req.N / (fixed_ms * 1e-3),
-                            "valu_tops": fixed_valu, "valu_frac": fixed_valu / PEAK_VALU_TOPS,
-                            "mfma_tflops": fixed_mfma, "mfma_frac": fixed_mfma / peak_mfma},
-        "roofline": roof,
-    }
-    if a.no_extras:
-        line["fixed_100_iters"] = None
-    elif prec == PREC_FP32 and not fixed:
-        # the reduced-precision forms on the same batch at the same residual target
-        side = {}
-        for name, p2 in (("bf16", PREC_BF16), ("fp16", PREC_FP16)):
-            o2 = options(precision=p2, alpha=a.alpha, tol=a.tol, check_every=a.check_every,
-                         fp32_tail=10)
-            w2, per2 = _timed(lambda: P.solve(x, req.q0, req.v0, n_it, opts=o2, out=out,
-                                              r_primal=rp, r_dual=rd, iters_out=it,
-                                              stream=stream), a.steps, a.warmup, stream)
-            res2 = np.maximum(rp.cpu().numpy(), rd.cpu().numpy())
-            it2 = it.cpu().numpy()
-            side[name + "+10fp32"] = {
-                "value": req.N / (w2 / a.steps), "ms_per_step": w2 * 1e3 / a.steps,
-                "latency_ms": {"p50": float(np.percentile(per2, 50)),
-                               "p99": float(np.percentile(per2, 99))},
-                "iterations": {"max": int(it2.max()), "mean": float(it2.mean()),
-                               "converged_frac": float(np.mean(res2 <= a.tol))}}
-        line["side_by_side"] = side
-    if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(req, a.tol, a.check_every, a.iters_cap, a.alpha,
-                                            a.cpu_sample, P.weights)
-    print(json.dumps(line), flush=True)
+    runners = {"all": run_all, "uneven": run_uneven, "serve": run_serve, "sigma": run_sigma,
+               "plan": run_plan, "literal": run_literal, "mpc": run_single, "long": run_single}
+    return runners[a.workload](a)
 
 
 if __name__ == "__main__":
