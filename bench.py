@@ -138,6 +138,9 @@ def parse():
                     help="all: per-controller rates (Hz) of the served-capacity sweep")
     ap.add_argument("--no-serve", action="store_true", help="all: skip the serving runs")
     ap.add_argument("--no-side", action="store_true", help="one form only (--precision)")
+    ap.add_argument("--tile-waves", type=int, default=0, choices=[0, 1, 2],
+                    help="waves per 16-sample tile of a single solve (options.tile_waves; "
+                    "0 = library's choice; the batch and serving paths take 0 or 1)")
     ap.add_argument("--cold", action="store_true", help="serve: no warm start (sample "
                     "counts alternate so no request matches its predecessor)")
     ap.add_argument("--copy-calibrate-mb", type=int, default=0,
@@ -307,7 +310,8 @@ def _prec(name):
 def form_options(a, form, fixed=False):
     from paper_2608_25666_amd import options
     return options(precision=_prec(form), alpha=a.alpha, tol=0.0 if fixed else a.tol,
-                   check_every=a.check_every, fp32_tail=0 if form == "fp32" else a.fp32_tail)
+                   check_every=a.check_every, fp32_tail=0 if form == "fp32" else a.fp32_tail,
+                   tile_waves=a.tile_waves)
 
 
 def _forms(a):

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PRISM_PROJ_ABI_VERSION 2
+#define PRISM_PROJ_ABI_VERSION 3
 #define PRISM_MAX_H 128          /* horizon limit: the x-update inverse is staged on-chip */
 #define PRISM_MAX_JOINTS 64
 
@@ -96,10 +96,22 @@ typedef struct {
                            (iteration 0, every check_every iterations, and iters)
                            where all its columns have max(r_primal, r_dual) <= tol */
   int32_t check_every;  /* residual check period (>= 1) when tol > 0                 */
-  int32_t reserved[3];  /* must be zero                                              */
+  int32_t tile_waves;   /* waves per 16-sample tile: 0 = the library's choice (one
+                           wave), 1 = one wave, 2 = a pair of waves of one workgroup
+                           (each holds half of the steps and computes half of the
+                           x-update, handing sums, boundary terms and its defect to
+                           the other through LDS). The pair shortens a lone H = 100
+                           FP32 tile's iteration by about a tenth; elsewhere the
+                           hand-overs cost more than the split saves. Two waves need
+                           H >= 16, a chunk size ceil(H/8) built into the library
+                           (3, 7 or 13), and no warm start or dual-state output;
+                           single solves only (PRISM_EUNSUPPORTED otherwise). Results
+                           are the same iteration with another FP32 summation order */
+  int32_t reserved[2];  /* must be zero                                              */
 } prism_options_t;
 
-/* Fill *opts with the defaults: FP32, fp32_tail 0, alpha 1, tol 0, check_every 10. */
+/* Fill *opts with the defaults: FP32, fp32_tail 0, alpha 1, tol 0, check_every 10,
+ * tile_waves 0. */
 void prism_options_default(prism_options_t* opts);
 
 /* prism_proj_create -- build the reusable factor for horizon H and step dt.

@@ -41,7 +41,8 @@ class Bounds(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp32_tail", C.c_int32), ("alpha", C.c_float),
-                ("tol", C.c_float), ("check_every", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("tol", C.c_float), ("check_every", C.c_int32), ("tile_waves", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class SolveArgs(C.Structure):

@@ -13,6 +13,7 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -44,17 +45,32 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _newest_header() -> float:
-    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
-    return max(os.path.getmtime(h) for h in hs) if hs else 0.0
+_INCLUDE_RE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
 
 
-def _compile(src: str, incremental: bool, hdr_time: float):
+def _newest_input(src: str) -> float:
+    """Newest modification time of src and the local headers it includes, recursively."""
+    seen, todo, newest = set(), [src], 0.0
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        newest = max(newest, os.path.getmtime(f))
+        with open(f, encoding="utf-8") as fh:
+            for name in _INCLUDE_RE.findall(fh.read()):
+                for d in (os.path.dirname(f), CSRC, INCLUDE):
+                    cand = os.path.join(d, name)
+                    if os.path.exists(cand):
+                        todo.append(cand)
+                        break
+    return newest
+
+
+def _compile(src: str, incremental: bool):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    if incremental and os.path.exists(obj):
-        ot = os.path.getmtime(obj)
-        if ot > os.path.getmtime(src) and ot > hdr_time:
-            return obj, 0.0, ""
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(src):
+        return obj, 0.0, ""
     cmd = [hipcc()] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -68,12 +84,11 @@ def build(jobs: int = 0, incremental: bool = False, verbose: bool = False) -> st
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = jobs or max(1, min(16, os.cpu_count() or 4))
-    hdr_time = _newest_header()
     srcs = sources()
     objs = []
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s, incremental, hdr_time): s for s in srcs}
+        futs = {ex.submit(_compile, s, incremental): s for s in srcs}
         for f in cf.as_completed(futs):
             obj, dt, err = f.result()
             objs.append(obj)

@@ -132,6 +132,16 @@ SolveKernelFn plan_kernel_f32(int HQ);
 SolveKernelFn plan_kernel_bf16(int HQ);
 SolveKernelFn plan_kernel_f16(int HQ);
 
+// Two-wave tile kernels (admm_pair.h) by chunk size HP = ceil(H/8); null if not built.
+// The launch takes kPairWaves waves per workgroup and pair_lds_words(HP) 32-bit words of
+// LDS per pair after the factor fragments.
+constexpr int kPairWaves = 8;
+constexpr int pair_lds_words(int HP) { return 244 + 4 * HP * 64; }
+using PairKernelFn = void (*)(SolveKernelArgs);
+PairKernelFn pair_kernel_f32(int HP);
+PairKernelFn pair_kernel_bf16(int HP);
+PairKernelFn pair_kernel_f16(int HP);
+
 // Kernel for chunk size HQ (2..32), exact fit (4*HQ == H) and GEMM precision.
 SolveKernelFn solve_kernel_f32(int HQ, bool exact);
 SolveKernelFn solve_kernel_bf16(int HQ, bool exact);

@@ -79,6 +79,7 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
                              const prism_options_t& opts, hipStream_t stream, int grid_pct) {
   prism_status_t st = validate_options(&opts);
   if (st != PRISM_OK) return st;
+  if (opts.tile_waves == 2) return PRISM_EUNSUPPORTED;   // batched launches use one-wave tiles
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return PRISM_EDEVICE;
 

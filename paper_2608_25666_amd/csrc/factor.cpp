@@ -173,6 +173,60 @@ void layout_16(const std::vector<double>& K, int H, int HQ, bool bf16, std::vect
         }
 }
 
+namespace {
+
+// Step of MFMA row `row` of member m's output block b (lane group row / 4 of the
+// member, chunk register 4b + row % 4), or -1 past the chunk or past H.
+inline int pair_out_row(int m, int b, int row, int HP, int H) {
+  const int reg = 4 * b + (row & 3);
+  const int step = (4 * m + (row >> 2)) * HP + reg;
+  return (reg < HP && step < H) ? step : -1;
+}
+
+// Step of k-index (lane group gk, register j) of source member ms.
+inline int pair_in_row(int ms, int gk, int j, int HP, int H) {
+  const int step = (4 * ms + gk) * HP + j;
+  return (j < HP && step < H) ? step : -1;
+}
+
+}  // namespace
+
+void layout_pair_f32(const std::vector<double>& K, int H, int HP, std::vector<float>& out) {
+  const int nb = (HP + 3) / 4, nj4 = (HP + 3) / 4;
+  const size_t per = pair_f32_frag_count(HP);
+  out.assign(2 * per, 0.0f);
+  for (int m = 0; m < 2; ++m)
+    for (int b = 0; b < nb; ++b)
+      for (int s = 0; s < 2; ++s)
+        for (int jj = 0; jj < nj4; ++jj)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 4; ++e) {
+              const int r = pair_out_row(m, b, lane & 15, HP, H);
+              const int c = pair_in_row(s == 0 ? m : 1 - m, lane >> 4, 4 * jj + e, HP, H);
+              const float v = (r >= 0 && c >= 0) ? (float)K[(size_t)r * H + c] : 0.0f;
+              out[m * per + ((((size_t)b * 2 + s) * nj4 + jj) * 64 + lane) * 4 + e] = v;
+            }
+}
+
+void layout_pair_16(const std::vector<double>& K, int H, int HP, bool bf16,
+                    std::vector<uint16_t>& out) {
+  const int nb = (HP + 3) / 4, nj8 = (HP + 7) / 8;
+  const size_t per = pair_16_frag_count(HP);
+  out.assign(2 * per, 0);
+  for (int m = 0; m < 2; ++m)
+    for (int b = 0; b < nb; ++b)
+      for (int s = 0; s < 2; ++s)
+        for (int jj = 0; jj < nj8; ++jj)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+              const int r = pair_out_row(m, b, lane & 15, HP, H);
+              const int c = pair_in_row(s == 0 ? m : 1 - m, lane >> 4, 8 * jj + e, HP, H);
+              const float v = (r >= 0 && c >= 0) ? (float)K[(size_t)r * H + c] : 0.0f;
+              out[m * per + ((((size_t)b * 2 + s) * nj8 + jj) * 64 + lane) * 8 + e] =
+                  bf16 ? float_to_bf16_rne(v) : float_to_f16_rne(v);
+            }
+}
+
 void layout_f64(const std::vector<double>& K, const std::vector<double>& k, int H, int HQ,
                 std::vector<double>& out) {
   const int nb = (HQ + 3) / 4, nj2 = (HQ + 1) / 2;

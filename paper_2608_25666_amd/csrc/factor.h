@@ -42,6 +42,25 @@ inline size_t f64_frag_count(int HQ) {
   return (size_t)((HQ + 3) / 4) * ((HQ + 1) / 2) * 64 * 2;
 }
 
+// Two-wave tiles: a tile's H steps are cut into eight chunks of HP = ceil(H / 8) rows;
+// member m of the pair of waves holds chunks 4m .. 4m+3 (lane group g: chunk 4m + g).
+// Member m's A-operand fragments cover its own output rows (NB = ceil(HP/4) blocks)
+// against the k-steps of both members' chunks, its own first (source s = 0) and then
+// its partner's (s = 1):
+//   FP32:   index m*F + (((b*2 + s)*NJ4 + jj)*64 + lane)*4 + e,  k-step j = 4jj + e,
+//   16-bit: index m*F + (((b*2 + s)*NJ8 + jj)*64 + lane)*8 + e,  k-step j = 8jj + e,
+// with F the per-member fragment count. Row and column steps past H are zero.
+inline int pair_chunk_rows(int H) { return (H + 7) / 8; }
+void layout_pair_f32(const std::vector<double>& K, int H, int HP, std::vector<float>& out);
+void layout_pair_16(const std::vector<double>& K, int H, int HP, bool bf16,
+                    std::vector<uint16_t>& out);
+inline size_t pair_f32_frag_count(int HP) {   // per member
+  return (size_t)((HP + 3) / 4) * 2 * ((HP + 3) / 4) * 64 * 4;
+}
+inline size_t pair_16_frag_count(int HP) {    // per member
+  return (size_t)((HP + 3) / 4) * 2 * ((HP + 7) / 8) * 64 * 8;
+}
+
 // Byte sizes of the two layouts.
 inline size_t f32_frag_bytes(int HQ) {
   const int nb = (HQ + 3) / 4;

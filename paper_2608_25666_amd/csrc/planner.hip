@@ -163,6 +163,7 @@ prism_status_t plan_step_impl(prism_proj_t p, const prism_plan_args_t* a, hipStr
   const prism_options_t* o = a->opts ? a->opts : &p->opts;
   prism_status_t st = validate_options(o);
   if (st != PRISM_OK) return st;
+  if (o->tile_waves == 2) return PRISM_EUNSUPPORTED;   // the optimizer step uses one-wave tiles
   if (a->N < 1 || a->iters < 0 || !a->q0 || !a->v0 || !a->nu || !a->sigma || !a->theta_ref ||
       !a->x_out || !a->nu_out || !a->var_out)
     return PRISM_EINVAL;

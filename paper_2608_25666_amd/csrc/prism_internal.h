@@ -35,11 +35,26 @@ struct prism_proj_s {
   prism::CounterRing<kCounterRing> ring;
   hipEvent_t ring_ev[kCounterRing] = {};   // completion of each set's last launch
   int f32_bytes = 0, b16_bytes = 0;
+  // two-wave tiles (H >= kPairMinH): eight chunks of HP rows, pair-layout fragments
+  int HP = 0;
+  void* pair_frag_bf16 = nullptr;   // device: FP32 pair fragments then BF16 pair fragments
+  void* pair_frag_f16 = nullptr;    // device: FP32 pair fragments then FP16 pair fragments
+  int pair_f32_bytes = 0, pair_b16_bytes = 0;
   std::mutex lit_mu;                              // guards lit
   std::vector<std::pair<double, double*>> lit;    // device factors of the printed iteration, per delta
 };
 
 namespace prism {
+
+constexpr int kPairMinH = 16;   // shortest horizon with two-wave tiles (chunks of >= 2 rows)
+
+// The two-wave tile kernel for a solve, or null when the solve cannot use it (horizon,
+// chunk size not built, warm start, dual state or sample drawing requested).
+PairKernelFn pick_pair_kernel(const prism_proj_s* p, int precision);
+int pair_lds_bytes(const prism_proj_s* p, int precision);
+// As launch_solve, for the two-wave tile kernel.
+prism_status_t launch_pair(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                           PairKernelFn fn, hipStream_t stream);
 
 // Frees the printed iteration's device factors of a handle.
 void release_literal_factors(prism_proj_s* p);

@@ -82,6 +82,7 @@ prism_status_t validate_options(const prism_options_t* o) {
   if (!(o->alpha > 0.0f && o->alpha < 2.0f)) return PRISM_EINVAL;
   if (!std::isfinite(o->tol)) return PRISM_EINVAL;
   if (o->check_every < 1) return PRISM_EINVAL;
+  if (o->tile_waves < 0 || o->tile_waves > 2) return PRISM_EINVAL;
   for (int r : o->reserved)
     if (r != 0) return PRISM_EINVAL;
   return PRISM_OK;
@@ -207,6 +208,76 @@ prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_opt
   return PRISM_OK;
 }
 
+PairKernelFn pick_pair_kernel(const prism_proj_s* p, int precision) {
+  if (p->HP == 0 || !p->pair_frag_bf16) return nullptr;
+  switch (precision) {
+    case PRISM_PREC_FP32: return pair_kernel_f32(p->HP);
+    case PRISM_PREC_BF16: return pair_kernel_bf16(p->HP);
+    case PRISM_PREC_FP16: return pair_kernel_f16(p->HP);
+    default: return nullptr;
+  }
+}
+
+int pair_lds_bytes(const prism_proj_s* p, int precision) {
+  const int frag = p->pair_f32_bytes + (precision == PRISM_PREC_FP32 ? 0 : p->pair_b16_bytes);
+  return frag + (kPairWaves / 2) * pair_lds_words(p->HP) * (int)sizeof(float);
+}
+
+prism_status_t launch_pair(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
+                           PairKernelFn fn, hipStream_t stream) {
+  const int tiles_per_joint = (K.N + kTileCols - 1) / kTileCols;
+  const long long ntiles = (long long)tiles_per_joint * p->nj;
+  if (ntiles > 0x7fffffff) return PRISM_EINVAL;
+  K.frag = (o->precision == PRISM_PREC_FP16) ? p->pair_frag_f16 : p->pair_frag_bf16;
+  K.H = p->H;
+  K.nj = p->nj;
+  K.ntiles = (int)ntiles;
+  K.check_every = o->check_every;
+  K.tolmode = (o->tol > 0.0f) ? 1 : 0;
+  K.tail = (o->precision == PRISM_PREC_FP32) ? 0 : std::min(o->fp32_tail, K.tolmode ? o->fp32_tail : K.iters);
+  K.rho = (float)(p->rho * p->w[2]);
+  K.cV = (float)(p->w[0] / p->w[2]);
+  K.cQ = (float)(p->w[1] / p->w[2]);
+  K.cJ = (float)(p->w[3] / p->w[2]);
+  K.alpha = o->alpha;
+  K.tol = o->tol;
+  K.frag_f32_bytes = p->pair_f32_bytes;
+  K.frag_16_bytes = p->pair_b16_bytes;
+  const int lds = pair_lds_bytes(p, o->precision);
+  if (lds > 160 * 1024) return PRISM_EUNSUPPORTED;
+  const int threads = kPairWaves * 64;
+  int bpc = 0;
+  {
+    if (lds > 64 * 1024) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, (const void*)fn, threads, lds) != hipSuccess ||
+        bpc <= 0)
+      bpc = 1;
+  }
+  const long long want = (ntiles + kPairWaves / 2 - 1) / (kPairWaves / 2);
+  const long long cap = (long long)bpc * num_cus();
+  const int grid = (int)std::max(1ll, std::min(want, cap));
+
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap_st) != hipSuccess) return PRISM_EDEVICE;
+  const bool capturing = cap_st != hipStreamCaptureStatusNone;
+  std::lock_guard<std::mutex> lk(p->ring_mu);
+  const auto t = p->ring.take();
+  K.counter = p->d_counters + (size_t)t.slot * kXcdQueues;
+  if (!capturing && t.wait && hipStreamWaitEvent(stream, p->ring_ev[t.slot], 0) != hipSuccess)
+    return PRISM_EDEVICE;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
+  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  void* params[] = {&K};
+  if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(threads), params, lds, stream) != hipSuccess)
+    return PRISM_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  if (!capturing) {
+    if (hipEventRecord(p->ring_ev[t.slot], stream) != hipSuccess) return PRISM_EDEVICE;
+    p->ring.recorded(t.slot);
+  }
+  return PRISM_OK;
+}
+
 }  // namespace prism
 
 // ---------------------------------------------------------------------------
@@ -310,8 +381,16 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
     delete p;
     return PRISM_EDEVICE;
   }
-  std::vector<float> f32;
-  std::vector<uint16_t> bf, hf;
+  std::vector<float> f32, pf32;
+  std::vector<uint16_t> bf, hf, pbf, phf;
+  if (H >= kPairMinH) {
+    p->HP = pair_chunk_rows(H);
+    layout_pair_f32(p->K, H, p->HP, pf32);
+    layout_pair_16(p->K, H, p->HP, true, pbf);
+    layout_pair_16(p->K, H, p->HP, false, phf);
+    p->pair_f32_bytes = (int)(pf32.size() * sizeof(float));
+    p->pair_b16_bytes = (int)(pbf.size() * sizeof(uint16_t));
+  }
   layout_f32(p->K, H, p->HQ, f32);
   layout_16(p->K, H, p->HQ, true, bf);
   layout_16(p->K, H, p->HQ, false, hf);
@@ -336,6 +415,21 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
         hipMemset(p->d_counters, 0, sizeof(int) * kCounterRing * kXcdQueues) != hipSuccess)
       st = PRISM_EDEVICE;
   }
+  if (st == PRISM_OK && p->HP > 0) {
+    const size_t ptot = (size_t)p->pair_f32_bytes + p->pair_b16_bytes;
+    if (hipMalloc(&p->pair_frag_bf16, ptot) != hipSuccess ||
+        hipMalloc(&p->pair_frag_f16, ptot) != hipSuccess) {
+      st = PRISM_ENOMEM;
+    } else {
+      char* a = (char*)p->pair_frag_bf16;
+      char* b = (char*)p->pair_frag_f16;
+      if (hipMemcpy(a, pf32.data(), p->pair_f32_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(a + p->pair_f32_bytes, pbf.data(), p->pair_b16_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b, pf32.data(), p->pair_f32_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b + p->pair_f32_bytes, phf.data(), p->pair_b16_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        st = PRISM_EDEVICE;
+    }
+  }
   for (int i = 0; st == PRISM_OK && i < kCounterRing; ++i)
     if (hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming) != hipSuccess)
       st = PRISM_EDEVICE;
@@ -353,6 +447,8 @@ void prism_proj_destroy(prism_proj_t p) {
   if (p->frag_f16) (void)hipFree(p->frag_f16);
   if (p->d_bounds) (void)hipFree(p->d_bounds);
   if (p->d_counters) (void)hipFree(p->d_counters);
+  if (p->pair_frag_bf16) (void)hipFree(p->pair_frag_bf16);
+  if (p->pair_frag_f16) (void)hipFree(p->pair_frag_f16);
   for (hipEvent_t& e : p->ring_ev)
     if (e) (void)hipEventDestroy(e);
   release_literal_factors(p);
@@ -408,8 +504,11 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   if (st != PRISM_OK) return st;
 
   const bool exact = (4 * p->HQ == p->H);
-  SolveKernelFn fn = pick_kernel(p->HQ, exact, o->precision);
-  if (!fn) return PRISM_EUNSUPPORTED;
+  const bool pair_ok = !a->x_warm && !a->state_warm && !a->state_out;
+  PairKernelFn pfn = (o->tile_waves == 2 && pair_ok) ? pick_pair_kernel(p, o->precision) : nullptr;
+  if (o->tile_waves == 2 && !pfn) return PRISM_EUNSUPPORTED;
+  SolveKernelFn fn = pfn ? nullptr : pick_kernel(p->HQ, exact, o->precision);
+  if (!fn && !pfn) return PRISM_EUNSUPPORTED;
   K.xin = a->v_samples;
   K.xout = a->v_out;
   K.rp = a->r_primal;
@@ -421,6 +520,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.shift = a->warm_shift;
   K.N = a->N;
   K.iters = a->iters;
+  if (pfn) return launch_pair(p, K, o, pfn, stream);
   return launch_solve(p, K, o, fn, stream);
 }
 

@@ -16,7 +16,7 @@ from . import _lib as L
 
 
 def options(precision: int = L.PREC_FP32, fp32_tail: int = 0, alpha: float = 1.0,
-            tol: float = 0.0, check_every: int = 10) -> L.Options:
+            tol: float = 0.0, check_every: int = 10, tile_waves: int = 0) -> L.Options:
     o = L.Options()
     L.lib().prism_options_default(C.byref(o))
     o.precision = precision
@@ -24,6 +24,7 @@ def options(precision: int = L.PREC_FP32, fp32_tail: int = 0, alpha: float = 1.0
     o.alpha = alpha
     o.tol = tol
     o.check_every = check_every
+    o.tile_waves = tile_waves
     return o
 
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.prism_abi_version() == 2
+    assert lib.prism_abi_version() == 3
 
 
 def test_status_strings_and_defaults():
