@@ -231,9 +231,12 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * Batched solve: many requests (each with its own handle, hence its own H,
  * joint count, dt, bounds and factor) in one persistent launch (Sec. III-D
  * "Batch parallelism": only the samples and right-hand sides differ between
- * QPs; here the factors may differ too). Requests are cut into work items of
- * four tiles (16 samples of one joint each) that share one factor; items are
- * ordered longest first and pulled by workgroups from an atomic counter.
+ * QPs; here the factors may differ too). Requests are ordered longest work
+ * first; each workgroup stages one request's factor and its waves claim that
+ * request's tiles (16 samples of one joint each) one at a time from per-XCD
+ * queues, the workgroup moving on to the first request with tiles left once
+ * its request is drained (workgroups start spread over the requests in
+ * proportion to their work).
  * A batch whose horizons all fall in {17..20, 49..52, 97..100} (chunk sizes
  * {5, 13, 25}) runs as one launch; other mixes run one launch per chunk-size
  * class (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the same stream.

@@ -20,7 +20,7 @@ struct prism_batch_s {
   JointRowParams* h_jp = nullptr;    // pinned
   BatchReq* d_reqs = nullptr;
   JointRowParams* d_jp = nullptr;
-  int* d_counters = nullptr;         // one per launch of a call (up to kMaxLaunches)
+  int* d_counters = nullptr;         // [cap_req][kXcdQueues] tile-queue counters
   size_t cap_req = 0, cap_jp = 0;
   hipEvent_t copied = nullptr;
   bool pending = false;
@@ -28,10 +28,9 @@ struct prism_batch_s {
 
 namespace {
 
-constexpr int kMaxLaunches = 8;   // chunk classes per call (6 used)
-
 __global__ void zero_ints_kernel(int* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 void release_tables(prism_batch_s* b) {
@@ -39,10 +38,12 @@ void release_tables(prism_batch_s* b) {
   if (b->h_jp) (void)hipHostFree(b->h_jp);
   if (b->d_reqs) (void)hipFree(b->d_reqs);
   if (b->d_jp) (void)hipFree(b->d_jp);
+  if (b->d_counters) (void)hipFree(b->d_counters);
   b->h_reqs = nullptr;
   b->h_jp = nullptr;
   b->d_reqs = nullptr;
   b->d_jp = nullptr;
+  b->d_counters = nullptr;
   b->cap_req = b->cap_jp = 0;
 }
 
@@ -53,7 +54,8 @@ prism_status_t reserve(prism_batch_s* b, size_t nreq, size_t njp) {
   if (hipHostMalloc((void**)&b->h_reqs, cr * sizeof(BatchReq), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&b->h_jp, cj * sizeof(JointRowParams), hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&b->d_reqs, cr * sizeof(BatchReq)) != hipSuccess ||
-      hipMalloc((void**)&b->d_jp, cj * sizeof(JointRowParams)) != hipSuccess) {
+      hipMalloc((void**)&b->d_jp, cj * sizeof(JointRowParams)) != hipSuccess ||
+      hipMalloc((void**)&b->d_counters, cr * kXcdQueues * sizeof(int)) != hipSuccess) {
     release_tables(b);
     return PRISM_ENOMEM;
   }
@@ -135,17 +137,21 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
 
   // ---- build the tables, grouped by launch
   struct Launch {
-    int set, first, count, items, hq_max, frag_max;
+    int set, first, count, hq_max, frag_max;
+    long long tiles;
+    double work;
   };
   std::vector<Launch> launches;
+  std::vector<int> live_of;   // request index of each table row
   size_t ri = 0, ji = 0;
   const bool tolmode = opts.tol > 0.0f;
   for (int s : sets) {
-    Launch L{s, (int)ri, 0, 0, 2, 0};
+    Launch L{s, (int)ri, 0, 2, 0, 0, 0.0};
     for (int r : live) {
       const BatchDesc& q = reqs[r];
       const prism_proj_s* p = q.p;
       if (!batch_set_has(s, p->HQ)) continue;
+      live_of.push_back(r);
       BatchReq& B = b->h_reqs[ri++];
       std::memset(&B, 0, sizeof(B));
       fill_joint_params(p, q.q0, q.v0, b->h_jp + ji);
@@ -179,16 +185,39 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
       B.HQ = p->HQ;
       B.frag_f32_bytes = p->f32_bytes;
       B.frag_16_bytes = p->b16_bytes;
-      B.tiles = ((q.N + kTileCols - 1) / kTileCols) * p->nj;
-      B.items = (B.tiles + kWaves - 1) / kWaves;
-      B.item_begin = L.items;
-      L.items += B.items;
+      B.nblk = (q.N + kTileCols - 1) / kTileCols;
+      B.wg_begin = 0;   // set below, once the launch's grid is known
+      L.tiles += (long long)B.nblk * p->nj;
+      L.work += cost(r);
       L.count++;
       L.hq_max = std::max(L.hq_max, p->HQ);
       L.frag_max = std::max(L.frag_max, solve_frag_bytes(p, opts.precision));
       ji += p->nj;
     }
     launches.push_back(L);
+  }
+
+  // ---- per launch: kernel, grid, and each request's first home workgroup (workgroups
+  // spread over the requests in proportion to their work, in launch order)
+  struct Plan {
+    BatchKernelFn fn;
+    int grid, lds;
+  };
+  std::vector<Plan> plans;
+  for (const Launch& L : launches) {
+    Plan P{pick_batch_kernel(L.set, opts.precision), 1, 0};
+    if (!P.fn) return PRISM_EUNSUPPORTED;
+    P.lds = L.frag_max + kWaves * L.hq_max * 64 * (int)sizeof(float);
+    const int bpc = kernel_blocks_per_cu((const void*)P.fn, P.lds);
+    const long long slots = std::max(1ll, (long long)bpc * device_cus() * grid_pct / 100);
+    P.grid = (int)std::max(1ll, std::min((L.tiles + kWaves - 1) / kWaves, slots));
+    double before = 0.0;
+    for (int k = 0; k < L.count; ++k) {
+      BatchReq& B = b->h_reqs[L.first + k];
+      B.wg_begin = (int)std::floor(before / L.work * P.grid);
+      before += cost(live_of[(size_t)(L.first + k)]);
+    }
+    plans.push_back(P);
   }
 
   // ---- upload tables, clear counters, launch
@@ -199,25 +228,22 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
       hipEventRecord(b->copied, stream) != hipSuccess)
     return PRISM_EDEVICE;
   b->pending = true;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, b->d_counters, kMaxLaunches);
+  const int n_ctr = (int)ri * kXcdQueues;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n_ctr + 255) / 256), dim3(256), 0, stream, b->d_counters,
+                     n_ctr);
   if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   for (size_t li = 0; li < launches.size(); ++li) {
     const Launch& L = launches[li];
-    BatchKernelFn fn = pick_batch_kernel(L.set, opts.precision);
-    if (!fn) return PRISM_EUNSUPPORTED;
+    const Plan& P = plans[li];
     BatchKernelArgs A{};
     A.reqs = b->d_reqs + L.first;
     A.n_req = L.count;
-    A.n_items = L.items;
-    A.counter = b->d_counters + li;
+    A.counter = b->d_counters + (size_t)L.first * kXcdQueues;
     A.xt_offset = L.frag_max;
     A.hq_max = L.hq_max;
-    const int lds = L.frag_max + kWaves * L.hq_max * 64 * (int)sizeof(float);
-    const int bpc = kernel_blocks_per_cu((const void*)fn, lds);
-    const long long slots = std::max(1ll, (long long)bpc * device_cus() * grid_pct / 100);
-    const int grid = (int)std::max(1ll, std::min((long long)L.items, slots));
     void* params[] = {&A};
-    if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) != hipSuccess)
+    if (hipLaunchKernel((const void*)P.fn, dim3(P.grid), dim3(kWaves * 64), params, P.lds, stream) !=
+        hipSuccess)
       return PRISM_EDEVICE;
     if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   }
@@ -236,8 +262,7 @@ prism_status_t prism_batch_create(prism_batch_t* out) {
     delete b;
     return PRISM_EDEVICE;
   }
-  if (hipMalloc((void**)&b->d_counters, kMaxLaunches * sizeof(int)) != hipSuccess ||
-      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
     prism_batch_destroy(b);
     return PRISM_ENOMEM;
   }
@@ -249,7 +274,6 @@ void prism_batch_destroy(prism_batch_t b) {
   if (!b) return;
   if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
   release_tables(b);
-  if (b->d_counters) (void)hipFree(b->d_counters);
   if (b->copied) (void)hipEventDestroy(b->copied);
   delete b;
 }

@@ -86,23 +86,21 @@ struct SolveKernelArgs {
   JointRowParams jp[kMaxJoints];
 };
 
-// One request of a batched launch (device memory). Its tiles are grouped in
-// work items of kWaves tiles that share the request's factor.
+// One request of a batched launch (device memory). Its sample blocks are dealt to
+// kXcdQueues tile queues (block b to queue b mod kXcdQueues), as in a single solve.
 struct BatchReq {
   TileArgs t;
   const void* frag;          // FP32 fragments, then 16-bit fragments
   int HQ;
   int frag_f32_bytes, frag_16_bytes;
-  int tiles;                 // ceil(N / 16) * n_joints
-  int item_begin;            // first global work item of this request
-  int items;                 // ceil(tiles / kWaves)
+  int nblk;                  // ceil(N / 16) sample blocks
+  int wg_begin;              // first workgroup whose home is this request
 };
 
 struct BatchKernelArgs {
-  const BatchReq* reqs;      // sorted so that item_begin is increasing
+  const BatchReq* reqs;      // longest work first; wg_begin non-decreasing
   int n_req;
-  int n_items;
-  int* counter;              // work-item counter, zero at launch
+  int* counter;              // [n_req][kXcdQueues] tile-queue counters, zero at launch
   int xt_offset;             // LDS byte offset of the per-wave sample copies
   int hq_max;                // largest chunk size in this launch
 };
