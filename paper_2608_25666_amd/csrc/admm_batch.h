@@ -44,6 +44,7 @@ __device__ __forceinline__ void batch_body(const BatchKernelArgs& B) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   float* xt_wave = reinterpret_cast<float*>(lds + B.xt_offset) + wave * (B.hq_max * 64);
+  if (B.n_req <= 0) return;
   const int xq = blockIdx.x & (kXcdQueues - 1);   // workgroups are dealt to XCDs round-robin
   int r = 0;                                      // home: last request with wg_begin <= blockIdx
   {
@@ -126,20 +127,23 @@ __global__ __launch_bounds__(256) void admm_batch_kernel(BatchKernelArgs B) {
 
 using BatchKernelFn = void (*)(BatchKernelArgs);
 
-// Kernels by chunk-size set: 0 = {5, 13, 25} (horizons 17-20, 49-52, 97-100),
-// 1 = chunks 2..8, 2 = 9..12, 3 = 13..16, 4 = 17..24, 5 = 25..32.
+// Kernels by chunk-size set: 0 = {5, 13} (horizons 17-20, 49-52; two waves per SIMD),
+// 6 = {25} (horizons 97-100; one wave), 1 = chunks 2..8, 2 = 9..12 (two waves),
+// 3 = 13..16, 4 = 17..24, 5 = 25..32 (one wave). A batch whose chunks all fall in
+// {5, 13, 25} runs sets 6 and 0; any other mix runs the classes 1..5 it uses.
 BatchKernelFn batch_kernel_f32(int set);
 BatchKernelFn batch_kernel_bf16(int set);
 BatchKernelFn batch_kernel_f16(int set);
 
 inline bool batch_set_has(int set, int hq) {
   switch (set) {
-    case 0: return hq == 5 || hq == 13 || hq == 25;
+    case 0: return hq == 5 || hq == 13;
     case 1: return hq >= 2 && hq <= 8;
     case 2: return hq >= 9 && hq <= 12;
     case 3: return hq >= 13 && hq <= 16;
     case 4: return hq >= 17 && hq <= 24;
     case 5: return hq >= 25 && hq <= 32;
+    case 6: return hq == 25;
     default: return false;
   }
 }

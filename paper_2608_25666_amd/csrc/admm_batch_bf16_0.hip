@@ -4,8 +4,9 @@
 namespace prism {
 
 BatchKernelFn batch_kernel_bf16_0(int set) {
-  if (set == 0) return admm_batch_kernel<GEMM_BF16, 5, 13, 25>;
+  if (set == 0) return admm_batch_kernel_2w<GEMM_BF16, 5, 13>;
   if (set == 1) return admm_batch_kernel_2w<GEMM_BF16, 2, 3, 4, 5, 6, 7, 8>;
+  if (set == 6) return admm_batch_kernel<GEMM_BF16, 25>;
   return nullptr;
 }
 

@@ -54,15 +54,15 @@ BatchKernelFn batch_kernel_f16_1(int set);
 BatchKernelFn batch_kernel_f16_2(int set);
 
 BatchKernelFn batch_kernel_f32(int set) {
-  if (set <= 1) return batch_kernel_f32_0(set);
+  if (set <= 1 || set == 6) return batch_kernel_f32_0(set);
   return set <= 3 ? batch_kernel_f32_1(set) : batch_kernel_f32_2(set);
 }
 BatchKernelFn batch_kernel_bf16(int set) {
-  if (set <= 1) return batch_kernel_bf16_0(set);
+  if (set <= 1 || set == 6) return batch_kernel_bf16_0(set);
   return set <= 3 ? batch_kernel_bf16_1(set) : batch_kernel_bf16_2(set);
 }
 BatchKernelFn batch_kernel_f16(int set) {
-  if (set <= 1) return batch_kernel_f16_0(set);
+  if (set <= 1 || set == 6) return batch_kernel_f16_0(set);
   return set <= 3 ? batch_kernel_f16_1(set) : batch_kernel_f16_2(set);
 }
 

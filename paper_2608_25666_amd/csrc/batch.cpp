@@ -114,19 +114,27 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
   };
   std::stable_sort(live.begin(), live.end(), [&](int a, int c) { return cost(a) > cost(c); });
 
-  // ---- which launches: one for the {5, 13, 25} set, else one per chunk class
+  // ---- which launches: sets 6 and 0 for chunks {5, 13, 25} only, else one per chunk class
   bool all_mpc = true;
   for (int r : live)
-    if (!batch_set_has(0, reqs[r].p->HQ)) all_mpc = false;
+    if (!batch_set_has(0, reqs[r].p->HQ) && !batch_set_has(6, reqs[r].p->HQ)) all_mpc = false;
   std::vector<int> sets;
-  if (all_mpc) sets.push_back(0);
-  else
+  if (all_mpc) {
+    // horizons 97-100 (one wave per SIMD), then 17-20 and 49-52 (two waves per SIMD)
+    for (int s : {6, 0})
+      for (int r : live)
+        if (batch_set_has(s, reqs[r].p->HQ)) {
+          sets.push_back(s);
+          break;
+        }
+  } else {
     for (int s = 1; s <= 5; ++s)
       for (int r : live)
         if (batch_set_has(s, reqs[r].p->HQ)) {
           sets.push_back(s);
           break;
         }
+  }
 
   if (b->pending) {
     if (hipEventSynchronize(b->copied) != hipSuccess) return PRISM_EDEVICE;
@@ -194,7 +202,7 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
       L.frag_max = std::max(L.frag_max, solve_frag_bytes(p, opts.precision));
       ji += p->nj;
     }
-    launches.push_back(L);
+    if (L.count > 0) launches.push_back(L);
   }
 
   // ---- per launch: kernel, grid, and each request's first home workgroup (workgroups
