@@ -117,7 +117,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time a fixed iteration count instead of the residual target")
-    ap.add_argument("--cpu-sample", type=int, default=1024,
+    ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="samples (all joints) for the oracle (uneven batch: this / 64 per request)")
     ap.add_argument("--workload", default="all",
                     choices=["all", "mpc", "long", "uneven", "serve", "sigma", "plan", "literal"])
@@ -169,8 +169,9 @@ def kernel_source_sha(literal: bool = False) -> str:
 
 
 def measured_traffic(key: str, sha: str = None):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, or None
-    when none were taken for this workload or the kernel sources changed since."""
+    """HBM bytes per step (the kernels of one call, summed) from the committed FETCH_SIZE /
+    WRITE_SIZE counters, or None when none were taken for this workload or the kernel
+    sources changed since."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             t = json.load(fh).get(key)
@@ -178,8 +179,8 @@ def measured_traffic(key: str, sha: str = None):
         return None
     if not t or t.get("source_sha256") != (sha or kernel_source_sha()):
         return None
-    return 1024.0 * (t["fetch_kib_per_dispatch"] * t["fetch_factor"] +
-                     t["write_kib_per_dispatch"] * t["write_factor"])
+    return 1024.0 * (t["fetch_kib_per_step"] * t["fetch_factor"] +
+                     t["write_kib_per_step"] * t["write_factor"])
 
 
 BLAS_ENV = ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")
@@ -225,7 +226,7 @@ def cpu_oracle_pool(tasks, label):
                 n += k
                 itmax = max(itmax, it)
                 done += 1
-                if done % 8 == 0 or done == len(futs):
+                if done % max(8, len(futs) // 10) == 0 or done == len(futs):
                     progress(f"{label}: {done}/{len(futs)} tasks, {time.perf_counter() - t0:.1f} s")
             wall = time.perf_counter() - t0
     finally:
@@ -251,16 +252,19 @@ def cpu_baseline(req, tol, check_every, cap, alpha, nsamp, weights):
                       f"max iterations {itmax}"}
 
 
-def cpu_baseline_batch(reqs, tol, check_every, cap, alpha, per_req, weights_of):
-    """The FP64 oracle on the first per_req samples of every request."""
-    tasks = [(r.samples[:per_req], r.H, r.dt, r.bounds, r.q0, r.v0, r.rho, alpha, cap, tol,
-              check_every, weights_of(r)) for r in reqs]
+def cpu_baseline_batch(reqs, tol, check_every, cap, alpha, per_req, weights_of, chunk=32):
+    """The FP64 oracle on the first per_req samples of every request, in tasks of chunk
+    samples of one request (longest first, so the pool's tail is short)."""
+    tasks = [(r.samples[c0:min(per_req, r.N, c0 + chunk)], r.H, r.dt, r.bounds, r.q0, r.v0,
+              r.rho, alpha, cap, tol, check_every, weights_of(r))
+             for r in sorted(reqs, key=lambda q: -q.H * q.H * q.nj)
+             for c0 in range(0, min(per_req, r.N), chunk)]
     n, dt, workers, itmax = cpu_oracle_pool(tasks, "cpu baseline")
     return {"value": n / dt, "unit": "trajectories/s", "cores": workers, "kind": "oracle",
             "sample": f"first {per_req} samples of each of the {len(reqs)} requests ({n} "
-                      f"trajectories), FP64 NumPy oracle to residual <= {tol:g}, one request per "
-                      f"task over {workers} single-threaded worker processes; {dt:.1f} s; max "
-                      f"iterations {itmax}"}
+                      f"trajectories), FP64 NumPy oracle to residual <= {tol:g}, {chunk} samples "
+                      f"of one request per task over {workers} single-threaded worker processes; "
+                      f"{dt:.1f} s; max iterations {itmax}"}
 
 
 def roofline(col_iters_by_H, kern_s, prec_is_f32):
@@ -281,6 +285,9 @@ def roofline(col_iters_by_H, kern_s, prec_is_f32):
                 "frac": ach / peak_mfma}
     roof["traffic"] = None
     roof["mfma_util"] = mflop / kern_s / 1e12 / peak_mfma
+    # FP32 VALU and MFMA instructions do not overlap on this chip (SQ_VALU_MFMA_COEXEC_CYCLES
+    # reads 0), so the two legs' times at peak add up: the fraction of that sum achieved
+    roof["serialized_frac"] = (t_valu + t_mfma) / kern_s
     return roof
 
 
