@@ -25,7 +25,7 @@ line):
   per form;
 * cpu_baseline: the FP64 oracle on a bounded sample of the uneven batch.
 Inputs are resident in HBM before timing starts. Block penalty weights
-prism_default_block_weights(H), over-relaxation 1.8.
+prism_default_block_weights(H, joints, dt, bounds), over-relaxation 1.8.
 
 Other workloads (one line each, --workload): mpc, long, uneven, serve, sigma (the
 single-joint diagnostic of Sec. III-C), plan (one optimizer iteration around the
@@ -107,7 +107,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=list(FORMS))
     ap.add_argument("--alpha", type=float, default=1.8)
     ap.add_argument("--weights", default="default", choices=["default", "unit"],
-                    help="block penalty weights: prism_default_block_weights(H) or all ones")
+                    help="block penalty weights: prism_default_block_weights(H, joints, dt, "
+                         "bounds) or all ones")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--iters-cap", type=int, default=20000)
@@ -444,9 +445,10 @@ class UnevenBatch:
                             f"samples, residual <= {a.tol:g}",
                 "requests": len(self.reqs), "trajectories": self.total,
                 "distinct_factors": len(shapes), "alpha": a.alpha,
-                "block_weights": "prism_default_block_weights(H)" if a.weights == "default"
-                                 else "unit", "tol": a.tol, "check_every": a.check_every,
-                "iters_cap": a.iters_cap, "reduced_forms_fp32_tail": a.fp32_tail}
+                "block_weights": ("prism_default_block_weights(H, joints, dt, bounds)"
+                                  if a.weights == "default" else "unit"),
+                "tol": a.tol, "check_every": a.check_every, "iters_cap": a.iters_cap,
+                "reduced_forms_fp32_tail": a.fp32_tail}
 
 
 class ServingSetup:

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PRISM_PROJ_ABI_VERSION 3
+#define PRISM_PROJ_ABI_VERSION 4
 #define PRISM_MAX_H 128          /* horizon limit: the x-update inverse is staged on-chip */
 #define PRISM_MAX_JOINTS 64
 
@@ -145,9 +145,19 @@ prism_status_t prism_proj_create(int H, int n_joints, double dt, const prism_bou
 prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_bounds_t* bounds,
                                     double rho, const double* block_weights, prism_proj_t* out);
 
-/* Recommended block weights for horizon H, for rho = 1 and alpha = 1.8:
- * (1.7, 2.125/H, 13.6, 17). Writes w[0..3]. */
-void prism_default_block_weights(int H, double* w);
+/* Recommended block weights for a problem family, for rho = 1 and alpha = 1.8:
+ * s (1.7, 2.125/H, 13.6, 17) with s = 0.024 / (J dt^2) clipped to [2^-4.5, 2^1.5],
+ * J the smallest jerk half-width (j_max - j_min) / 2 over the joints. J dt^2 is
+ * the jerk bound in the rows' velocity units; the block ratios were tuned where
+ * it is 0.024 (|j| <= 60 rad/s^3 at dt = 0.02, s = 1), and the best uniform scale
+ * falls in proportion as that bound widens (sweeps over dt 0.02-0.1, jerk bounds
+ * 15-960, velocity bounds 1-3.14, acceleration bounds 2-32, H 15-100). The
+ * weights change the iteration's path, never its fixed point (the projection).
+ * Writes w[0..3]; PRISM_EINVAL for H outside 2..PRISM_MAX_H, a bad joint count,
+ * dt not positive and finite, missing bounds or a jerk width that is not
+ * positive and finite (nothing written then). */
+prism_status_t prism_default_block_weights(int H, int n_joints, double dt,
+                                           const prism_bounds_t* bounds, double* w);
 
 /* Set the handle's default options (used by prism_proj_solve). Not safe to
  * call while another thread issues solves on the same handle. */

@@ -136,7 +136,8 @@ def load(path: str = LIB_PATH):
                                    C.POINTER(H)]),
         "prism_proj_create_ex": (st, [C.c_int, C.c_int, C.c_double, C.POINTER(Bounds),
                                       C.c_double, C.POINTER(C.c_double), C.POINTER(H)]),
-        "prism_default_block_weights": (None, [C.c_int, C.POINTER(C.c_double)]),
+        "prism_default_block_weights": (C.c_int, [C.c_int, C.c_int, C.c_double, C.POINTER(Bounds),
+                                                 C.POINTER(C.c_double)]),
         "prism_proj_get_weights": (st, [H, C.POINTER(C.c_double)]),
         "prism_proj_set_options": (st, [H, C.POINTER(Options)]),
         "prism_proj_get_options": (st, [H, C.POINTER(Options)]),

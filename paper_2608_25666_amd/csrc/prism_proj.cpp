@@ -320,15 +320,29 @@ bool valid_weights(const double* w) {
 }
 }  // namespace
 
-void prism_default_block_weights(int H, double* w) {
-  if (!w) return;
-  const int h = H < 2 ? 2 : H;
-  // 1.7 * (1, 1.25/H, 8, 10): the slowest 16-sample group's iteration count at
-  // residual 1e-3 with alpha = 1.8, minimised over a sweep of eight workload shapes
-  w[0] = 1.7;
-  w[1] = 2.125 / h;
-  w[2] = 13.6;
-  w[3] = 17.0;
+prism_status_t prism_default_block_weights(int H, int n_joints, double dt,
+                                           const prism_bounds_t* bounds, double* w) {
+  if (!w || !bounds || !bounds->j_min || !bounds->j_max || H < 2 || H > PRISM_MAX_H ||
+      n_joints < 1 || n_joints > PRISM_MAX_JOINTS || !(dt > 0.0) || !is_fin(dt))
+    return PRISM_EINVAL;
+  double jw = 0.0;   // the smallest jerk half-width over the joints
+  for (int j = 0; j < n_joints; ++j) {
+    const double h = 0.5 * (bounds->j_max[j] - bounds->j_min[j]);
+    if (!(h > 0.0) || !is_fin(h)) return PRISM_EINVAL;
+    if (j == 0 || h < jw) jw = h;
+  }
+  // 1.7 * (1, 1.25/H, 8, 10) was tuned (the slowest 16-sample group's iteration count at
+  // residual 1e-3 with alpha = 1.8, over eight workload shapes) where the jerk bound in
+  // velocity units, jw dt^2, is 60 * 0.02^2; the best uniform scale of the weights falls
+  // in proportion as that bound widens
+  const double ref = 60.0 * 0.02 * 0.02;
+  double s = ref / (jw * dt * dt);
+  s = std::min(std::max(s, std::exp2(-4.5)), std::exp2(1.5));
+  w[0] = 1.7 * s;
+  w[1] = 2.125 / H * s;
+  w[2] = 13.6 * s;
+  w[3] = 17.0 * s;
+  return PRISM_OK;
 }
 
 prism_status_t prism_factor_host(int H, double rho, const double* w, double* K, double* k) {

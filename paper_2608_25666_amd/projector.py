@@ -72,10 +72,13 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-def default_block_weights(H: int):
-    """prism_default_block_weights: recommended (velocity, position, acceleration, jerk) weights."""
+def default_block_weights(H: int, n_joints: int, dt: float, bounds):
+    """prism_default_block_weights: recommended (velocity, position, acceleration, jerk)
+    weights for horizon H, step dt and the joints' bounds."""
     w = (C.c_double * 4)()
-    L.lib().prism_default_block_weights(int(H), w)
+    b, keep = _bounds_struct(bounds, int(n_joints))
+    L.check(L.lib().prism_default_block_weights(int(H), int(n_joints), float(dt), C.byref(b), w),
+            "prism_default_block_weights")
     return tuple(w)
 
 
@@ -83,7 +86,7 @@ class Projector:
     """Handle for one (H, joints, dt, bounds, rho, block weights) problem family.
 
     weights: None for the scalar penalty (prism_proj_create), "default" for
-    prism_default_block_weights(H), or four positive numbers.
+    prism_default_block_weights(H, n_joints, dt, bounds), or four positive numbers.
     """
 
     def __init__(self, H: int, n_joints: int, dt: float, bounds, rho: float = 1.0,
@@ -91,7 +94,7 @@ class Projector:
         self.H, self.nj, self.dt, self.rho = int(H), int(n_joints), float(dt), float(rho)
         self.bounds = bounds
         if isinstance(weights, str) and weights == "default":
-            weights = default_block_weights(self.H)
+            weights = default_block_weights(self.H, self.nj, self.dt, bounds)
         self.weights = None if weights is None else tuple(float(v) for v in weights)
         b, keep = _bounds_struct(bounds, self.nj)
         h = C.c_void_p()

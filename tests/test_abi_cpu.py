@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.prism_abi_version() == 3
+    assert lib.prism_abi_version() == 4
 
 
 def test_status_strings_and_defaults():
@@ -98,11 +98,47 @@ def test_create_rejects_inverted_or_nonfinite_bounds():
     assert lib.prism_proj_create(10, 3, 0.1, None, 1.0, C.byref(h)) == L.PRISM_EINVAL
 
 
+def _jerk_bounds(jerk):
+    """Bounds with the given per-joint jerk half-widths (the other limits loose)."""
+    nj = len(jerk)
+    L, _ = _lib()
+    arrs = [(C.c_double * nj)(*v) for v in
+            ([-7.0] * nj, [7.0] * nj, [-3.0] * nj, [3.0] * nj, [-8.0] * nj, [8.0] * nj,
+             [-j for j in jerk], list(jerk))]
+    return L.Bounds(*[C.cast(a, C.POINTER(C.c_double)) for a in arrs]), arrs
+
+
 def test_default_block_weights_and_weight_validation():
     L, lib = _lib()
     w = (C.c_double * 4)()
-    lib.prism_default_block_weights(50, w)
+    # the tuned point: jerk bound 60 rad/s^3 at dt = 0.02, i.e. 0.024 rad/s per step^2
+    b, keep = _jerk_bounds([60.0] * 12)
+    assert lib.prism_default_block_weights(50, 12, 0.02, C.byref(b), w) == L.PRISM_OK
     assert tuple(w) == (1.7, 2.125 / 50, 13.6, 17.0)
+    # dt = 0.05: the jerk bound in velocity units is 6.25x wider, the weights 6.25x smaller
+    assert lib.prism_default_block_weights(20, 12, 0.05, C.byref(b), w) == L.PRISM_OK
+    np.testing.assert_allclose(tuple(w), np.array((1.7, 2.125 / 20, 13.6, 17.0)) / 6.25,
+                               rtol=1e-14)
+    # the smallest jerk half-width over the joints decides; asymmetric bounds by half-width
+    b, keep = _jerk_bounds([120.0, 30.0, 60.0])
+    assert lib.prism_default_block_weights(50, 3, 0.02, C.byref(b), w) == L.PRISM_OK
+    np.testing.assert_allclose(w[0], 1.7 * 2.0, rtol=1e-14)
+    # clipped to [2^-4.5, 2^1.5]
+    b, keep = _jerk_bounds([6000.0])
+    assert lib.prism_default_block_weights(50, 1, 0.02, C.byref(b), w) == L.PRISM_OK
+    np.testing.assert_allclose(w[0], 1.7 * 2.0 ** -4.5, rtol=1e-14)
+    b, keep = _jerk_bounds([1.0])
+    assert lib.prism_default_block_weights(50, 1, 0.02, C.byref(b), w) == L.PRISM_OK
+    np.testing.assert_allclose(w[0], 1.7 * 2.0 ** 1.5, rtol=1e-14)
+    # bad arguments write nothing
+    w[0] = -1.0
+    for args in ((1, 1, 0.02), (129, 1, 0.02), (50, 0, 0.02), (50, 65, 0.02), (50, 1, 0.0),
+                 (50, 1, float("nan"))):
+        assert lib.prism_default_block_weights(*args, C.byref(b), w) == L.PRISM_EINVAL
+    assert lib.prism_default_block_weights(50, 1, 0.02, None, w) == L.PRISM_EINVAL
+    b0, keep0 = _jerk_bounds([0.0])
+    assert lib.prism_default_block_weights(50, 1, 0.02, C.byref(b0), w) == L.PRISM_EINVAL
+    assert w[0] == -1.0
     b, keep = _bounds(2)
     h = C.c_void_p()
     bad = (C.c_double * 4)(1.0, 0.0, 1.0, 1.0)
