@@ -20,7 +20,7 @@ line):
   shift, HBM-budget admission): served trajectories/s and p50/p99 request latency
   (arrival to completion) for FP32 and BF16 + FP32 tail; the top-level latency_ms
   is this run's FP32 request latency;
-* workloads.served_capacity: the same controllers at rising rates (8 s of arrivals
+* workloads.served_capacity: the same controllers at rising rates (6 s of arrivals
   each) until p99 exceeds one 20 Hz period (50 ms): the highest rate that keeps it,
   per form;
 * cpu_baseline: the FP64 oracle on a bounded sample of the uneven batch.
@@ -118,7 +118,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="time a fixed iteration count instead of the residual target")
-    ap.add_argument("--cpu-sample", type=int, default=10240,
+    ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="samples (all joints) for the oracle (uneven batch: this / 64 per request)")
     ap.add_argument("--workload", default="all",
                     choices=["all", "mpc", "long", "uneven", "serve", "sigma", "plan", "literal"])
@@ -133,9 +133,9 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: warm-state pool")
     ap.add_argument("--grid-share", type=int, default=75, help="serve: percent of workgroup "
                     "slots one launch may take")
-    ap.add_argument("--sweep-seconds", type=float, default=8.0,
+    ap.add_argument("--sweep-seconds", type=float, default=6.0,
                     help="all: seconds of arrivals per served-capacity point (0: skip)")
-    ap.add_argument("--sweep-rates", default="20,25,30,35,40,45,50,60,70,80,100",
+    ap.add_argument("--sweep-rates", default="20,30,40,50,60,70,80,100,120,140,160",
                     help="all: per-controller rates (Hz) of the served-capacity sweep")
     ap.add_argument("--no-serve", action="store_true", help="all: skip the serving runs")
     ap.add_argument("--no-side", action="store_true", help="one form only (--precision)")
