@@ -248,10 +248,13 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * its request is drained (workgroups start spread over the requests in
  * proportion to their work).
  * A batch whose horizons all fall in {17..20, 49..52, 97..100} (chunk sizes
- * {5, 13, 25}) runs as two launches: horizons 97..100 (one wave per SIMD),
- * then 17..20 and 49..52 (two waves per SIMD); other mixes run one launch per
- * chunk-size class (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the
- * same stream.
+ * {5, 13, 25}) runs as two launches: horizons 97..100 (one wave per SIMD) on
+ * the caller's stream and 17..20 and 49..52 (two waves per SIMD) on an
+ * internal stream of the staging object, forked from the caller's stream after
+ * the tables are uploaded and joined back to it, so the second launch fills the
+ * CUs the first one frees; other mixes run one launch per chunk-size class
+ * (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the caller's stream.
+ * Either way the caller's stream is ordered after the whole batch.
  * ------------------------------------------------------------------------- */
 typedef struct prism_batch_s* prism_batch_t;   /* staging buffers for request tables */
 

@@ -24,6 +24,10 @@ struct prism_batch_s {
   size_t cap_req = 0, cap_jp = 0;
   hipEvent_t copied = nullptr;
   bool pending = false;
+  // second launch of a split batch: an internal stream forked from the caller's stream
+  // after the tables and counters are ready and joined back after its launch
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -240,6 +244,19 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
   hipLaunchKernelGGL(zero_ints_kernel, dim3((n_ctr + 255) / 256), dim3(256), 0, stream, b->d_counters,
                      n_ctr);
   if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
+  // The {5, 13, 25} split's two launches are independent (disjoint requests, counters
+  // and outputs): the second runs on the internal stream, so its workgroups take the
+  // CUs that the first launch's workgroups free while its last tiles finish. Other
+  // mixes run their launches in order on the caller's stream.
+  const bool fork = all_mpc && launches.size() == 2;
+  if (fork) {
+    if (!b->side && (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+                     hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                     hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess))
+      return PRISM_EDEVICE;
+    if (hipEventRecord(b->fork, stream) != hipSuccess || hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess)
+      return PRISM_EDEVICE;
+  }
   for (size_t li = 0; li < launches.size(); ++li) {
     const Launch& L = launches[li];
     const Plan& P = plans[li];
@@ -250,11 +267,14 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
     A.xt_offset = L.frag_max;
     A.hq_max = L.hq_max;
     void* params[] = {&A};
-    if (hipLaunchKernel((const void*)P.fn, dim3(P.grid), dim3(kWaves * 64), params, P.lds, stream) !=
-        hipSuccess)
+    hipStream_t s = (fork && li == 1) ? b->side : stream;
+    if (hipLaunchKernel((const void*)P.fn, dim3(P.grid), dim3(kWaves * 64), params, P.lds, s) != hipSuccess)
       return PRISM_EDEVICE;
     if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
   }
+  if (fork && (hipEventRecord(b->join, b->side) != hipSuccess ||
+               hipStreamWaitEvent(stream, b->join, 0) != hipSuccess))
+    return PRISM_EDEVICE;
   return PRISM_OK;
 }
 
@@ -283,6 +303,12 @@ void prism_batch_destroy(prism_batch_t b) {
   if (b->pending && b->copied) (void)hipEventSynchronize(b->copied);
   release_tables(b);
   if (b->copied) (void)hipEventDestroy(b->copied);
+  if (b->side) {
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamDestroy(b->side);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
   delete b;
 }
 
