@@ -254,7 +254,8 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * the tables are uploaded and joined back to it, so the second launch fills the
  * CUs the first one frees; other mixes run one launch per chunk-size class
  * (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the caller's stream.
- * Either way the caller's stream is ordered after the whole batch.
+ * Either way the caller's stream is ordered after the whole batch. (The server's
+ * launches, which overlap on streams of their own, keep both on one stream.)
  * ------------------------------------------------------------------------- */
 typedef struct prism_batch_s* prism_batch_t;   /* staging buffers for request tables */
 

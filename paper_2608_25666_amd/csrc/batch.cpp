@@ -247,8 +247,9 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
   // The {5, 13, 25} split's two launches are independent (disjoint requests, counters
   // and outputs): the second runs on the internal stream, so its workgroups take the
   // CUs that the first launch's workgroups free while its last tiles finish. Other
-  // mixes run their launches in order on the caller's stream.
-  const bool fork = all_mpc && launches.size() == 2;
+  // mixes, and launches given a share of the GPU (the server's, which already overlap
+  // on up to four streams of their own), run in order on the caller's stream.
+  const bool fork = all_mpc && launches.size() == 2 && grid_pct >= 100;
   if (fork) {
     if (!b->side && (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
                      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
