@@ -162,3 +162,36 @@ def test_batch_warm_shift_equals_single():
     B.close()
     for P in projs:
         P.close()
+
+
+def test_split_batch_orders_the_callers_stream():
+    """A {20, 50, 100} batch runs its H = 20/50 launch on a stream forked from the
+    caller's: work queued on the caller's stream after the call (here a copy of every
+    output, with no device-wide synchronisation in between) must see the finished
+    results of both launches, on a non-default stream and on two calls in a row."""
+    import torch
+    from paper_2608_25666_amd import Batch, Projector, options, PREC_FP32
+    reqs = _small_mix(31, n_choices=(512, 1024), n_requests=6)
+    assert {r.H for r in reqs} >= {100} and {r.H for r in reqs} & {20, 50}
+    projs = [Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default") for r in reqs]
+    xs = [torch.from_numpy(np.ascontiguousarray(r.samples)).cuda() for r in reqs]
+    opts = options(precision=PREC_FP32, alpha=1.8, tol=1e-3, check_every=10)
+    ref = []
+    for P, x, r in zip(projs, xs, reqs):
+        o, _, _ = P.solve(x, r.q0, r.v0, 5000, opts=opts)
+        torch.cuda.synchronize()
+        ref.append(o.cpu().numpy())
+    B = Batch()
+    s = torch.cuda.Stream()
+    for rep in range(2):
+        with torch.cuda.stream(s):
+            outs = [torch.full_like(x, float("nan")) for x in xs]
+            B.solve([dict(proj=P, samples=x, q0=r.q0, v0=r.v0, iters=5000, out=o)
+                     for P, x, r, o in zip(projs, xs, reqs, outs)], opts=opts, stream=s)
+            copies = [o.clone() for o in outs]      # queued on s behind the batch
+        s.synchronize()
+        for c, want in zip(copies, ref):
+            np.testing.assert_array_equal(c.cpu().numpy(), want)
+    B.close()
+    for P in projs:
+        P.close()
