@@ -195,3 +195,59 @@ def test_split_batch_orders_the_callers_stream():
     B.close()
     for P in projs:
         P.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_uneven_batch_bench_settings_sampled(prec):
+    """The 64-request uneven batch in one call as the benchmark runs it: each request's
+    default block weights (scaled by its jerk bound and dt), alpha 1.8, residual <= 1e-3
+    checked every 10, reduced forms with 10 FP32 iterations after convergence. Every
+    column must meet the tolerance; the first and last tiles of an H = 100 and an H = 50
+    request at dt = 0.05 and of H = 100 and H = 20 requests at dt = 0.02, on their slowest
+    joint and one other, against the oracle run to the reported counts (tests/stops.py)."""
+    import torch
+    from paper_2608_25666_amd import Batch, Projector, options, PREC_BF16, PREC_FP16, PREC_FP32
+    from stops import check_residual_mode
+    from test_gpu_forms import TOL_REDUCED_RESIDUAL
+    p = {"fp32": PREC_FP32, "fp16": PREC_FP16, "bf16": PREC_BF16}[prec]
+    reqs = W.uneven_requests()
+    handles = {}
+    items, outs = [], []
+    for r in reqs:
+        key = (r.H, r.nj, r.dt)
+        if key not in handles:
+            handles[key] = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+        x = torch.from_numpy(r.samples).cuda()
+        it = torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda")
+        items.append(dict(proj=handles[key], samples=x, q0=r.q0, v0=r.v0, iters=20000, iters_out=it))
+        outs.append(it)
+    o = options(precision=p, alpha=1.8, tol=1e-3, check_every=10,
+                fp32_tail=0 if prec == "fp32" else 10)
+    B = Batch()
+    res = B.solve(items, opts=o)
+    torch.cuda.synchronize()
+    for (x, rp, rd) in res:
+        assert np.all(np.maximum(rp.cpu().numpy(), rd.cpu().numpy()) <= 1e-3)
+    picks = {}
+    for k, r in enumerate(reqs):
+        key = (r.H, r.dt)
+        if key in ((100, 0.05), (50, 0.05), (100, 0.02), (20, 0.02)) and key not in picks \
+                and r.N >= 512:
+            picks[key] = k
+    assert len(picks) == 4
+    for key, k in sorted(picks.items()):
+        r = reqs[k]
+        x, rp, rd = res[k]
+        itg = outs[k].cpu().numpy()
+        rows = np.r_[np.arange(0, 16), np.arange(r.N - 16, r.N)]
+        joints = sorted({int(np.argmax(itg.max(axis=0))), 0})
+        w = handles[(r.H, r.nj, r.dt)].weights
+        check_residual_mode(x.cpu().numpy()[rows], rp.cpu().numpy()[rows], rd.cpu().numpy()[rows],
+                            itg[rows], rows, r.samples, r.H, r.dt, r.bounds, r.q0, r.v0,
+                            tol=1e-3, check_every=10, cap=20000, alpha=1.8, weights=w,
+                            xbar=1e-4 if prec == "fp32" else TOL_REDUCED_RESIDUAL,
+                            check_stops=prec == "fp32",
+                            label=f"uneven request {k} H={r.H} dt={r.dt} {prec}", joints=joints)
+    B.close()
+    for P in handles.values():
+        P.close()
