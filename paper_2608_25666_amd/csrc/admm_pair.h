@@ -2,7 +2,7 @@
 // pair of waves of one workgroup, each holding half of the steps, so that the rows and
 // the x-update of one iteration are split between two SIMDs.
 //
-// Measured on MI355X (per iteration, a lone tile, FP32): H = 100 3.9 us against 4.3 us
+// Measured on MI355X (per iteration, a lone tile, FP32): H = 100 3.8 us against 4.2 us
 // for one wave; H = 50 2.1 against 1.6; H = 20 1.4 against 0.6. The iteration's
 // dependency chain (member 1's rows and defect, a hand-over, member 0's defect, a
 // hand-over, the x-update) keeps the per-iteration shuffles and LDS round trips serial,
@@ -499,7 +499,11 @@ struct PairSolver {
       rp_c = fmaxf(rp_own, P[L::RP + o]);
       rd_c = fmaxf(rd_own, P[L::RD + o]);
       bad_c = badl | Pi[L::BAD + o];
-      res_out = pair_wave_max(col_ok ? fmaxf(rp_c, rd_c) : 0.0f);
+      // uniform stop test up to HP = 7; at HP = 13 the scalar registers it frees are not
+      // worth the vector registers it costs there (256 with 13 spilled)
+      const float rmax = col_ok ? fmaxf(rp_c, rd_c) : 0.0f;
+      if constexpr (HP <= 7) res_out = pair_wave_max(rmax);
+      else res_out = wave_max(rmax);
     }
     return true;
   }
