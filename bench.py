@@ -153,7 +153,9 @@ def parse():
 def kernel_source_sha(literal: bool = False) -> str:
     """sha256 over the device sources of a kernel, as recorded beside the rocprofv3
     counters in profiles/traffic.json: kernel_args.h with admm_*.h and admm_*.hip for
-    the projection kernels, kernel_args.h with literal.hip for the printed iteration."""
+    the projection kernels (the two-wave tile sources admm_pair* excepted: the measured
+    launches do not include them), kernel_args.h with literal.hip for the printed
+    iteration."""
     import hashlib
     d = os.path.join(ROOT, "paper_2608_25666_amd", "csrc")
     h = hashlib.sha256()
@@ -161,7 +163,8 @@ def kernel_source_sha(literal: bool = False) -> str:
         if literal:
             own = f in ("kernel_args.h", "literal.hip")
         else:
-            own = f == "kernel_args.h" or (f.startswith("admm_") and f[-2:] in (".h", "ip"))
+            own = f == "kernel_args.h" or (f.startswith("admm_") and not f.startswith("admm_pair")
+                                           and f[-2:] in (".h", "ip"))
         if own:
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
