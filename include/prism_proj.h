@@ -153,6 +153,10 @@ prism_status_t prism_proj_create_ex(int H, int n_joints, double dt, const prism_
  * falls in proportion as that bound widens (sweeps over dt 0.02-0.1, jerk bounds
  * 15-960, velocity bounds 1-3.14, acceleration bounds 2-32, H 15-100). The
  * weights change the iteration's path, never its fixed point (the projection).
+ * They assume the position rows rarely bind; for requests whose trajectories run
+ * into the position limits a position weight w[1] 4x (dt = 0.02) to 16x (dt =
+ * 0.05) larger converged 3-12x faster in the same sweeps, at a cost where the
+ * positions stay clear (a handle with such weights via prism_proj_create_ex).
  * Writes w[0..3]; PRISM_EINVAL for H outside 2..PRISM_MAX_H, a bad joint count,
  * dt not positive and finite, missing bounds or a jerk width that is not
  * positive and finite (nothing written then). */
