@@ -206,6 +206,18 @@ def _cpu_oracle_task(t):
     return samples.shape[0], int(O.iters.max()), time.perf_counter() - t0
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_oracle_pool(tasks, label):
     """The FP64 oracle on the host cores: one single-threaded worker process per core
     (at most 16, the GPU machine's CPU share), the tasks (requests or slices of one) spread
@@ -250,7 +262,7 @@ def cpu_baseline(req, tol, check_every, cap, alpha, nsamp, weights):
               tol, check_every, weights) for c0 in range(0, S.shape[0], chunk)]
     n, dt, workers, itmax = cpu_oracle_pool(tasks, "cpu baseline")
     return {"value": n / dt, "unit": "trajectories/s", "cores": workers, "kind": "oracle",
-            "sample": f"first {n} samples x {req.nj} joints of the benchmark batch, FP64 NumPy "
+            "cpu": cpu_model(), "sample": f"first {n} samples x {req.nj} joints of the benchmark batch, FP64 NumPy "
                       f"oracle to residual <= {tol:g} (check every {check_every}), {chunk} samples "
                       f"per task over {workers} single-threaded worker processes; {dt:.1f} s; "
                       f"max iterations {itmax}"}
@@ -265,7 +277,7 @@ def cpu_baseline_batch(reqs, tol, check_every, cap, alpha, per_req, weights_of, 
              for c0 in range(0, min(per_req, r.N), chunk)]
     n, dt, workers, itmax = cpu_oracle_pool(tasks, "cpu baseline")
     return {"value": n / dt, "unit": "trajectories/s", "cores": workers, "kind": "oracle",
-            "sample": f"first {per_req} samples of each of the {len(reqs)} requests ({n} "
+            "cpu": cpu_model(), "sample": f"first {per_req} samples of each of the {len(reqs)} requests ({n} "
                       f"trajectories), FP64 NumPy oracle to residual <= {tol:g}, {chunk} samples "
                       f"of one request per task over {workers} single-threaded worker processes; "
                       f"{dt:.1f} s; max iterations {itmax}"}
@@ -932,7 +944,7 @@ def run_literal(a):
         except Exception:
             cores = 1
         line["cpu_baseline"] = {"value": N / dt_cpu, "unit": "trajectories/s",
-                                "cores": cores, "kind": "oracle",
+                                "cores": cores, "kind": "oracle", "cpu": cpu_model(),
                                 "sample": f"the whole batch ({N} samples x {nj} joints), "
                                           f"oracle literal_joint, {dt_cpu:.1f} s"}
     print(json.dumps(line), flush=True)
