@@ -89,7 +89,14 @@ typedef struct {
                            0) exactly fp32_tail FP32 iterations follow (check points
                            inside them do not stop the group), and the group stops
                            at their end if it meets tol there, else at the first
-                           later check point that does, staying in FP32           */
+                           later check point that does, staying in FP32. A group
+                           whose max residual at a check point exceeds 64 times
+                           the lowest it had at an earlier one enters that FP32
+                           phase there (tail included): near alpha = 2 the
+                           rounded x-update can make the iterates diverge (BF16
+                           at alpha 1.9 and 1.95 measured; FP16 did not).
+                           Fixed-count runs have no such guard: keep alpha <=
+                           1.85 for BF16 there                                    */
   float alpha;          /* over-relaxation in (0, 2); 1 = plain ADMM                 */
   float tol;            /* <= 0: run exactly `iters` iterations. > 0: each group of
                            16 samples of one joint stops at the first check point
@@ -257,7 +264,8 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* arg
  * internal stream of the staging object, forked from the caller's stream after
  * the tables are uploaded and joined back to it, so the second launch fills the
  * CUs the first one frees; other mixes run one launch per chunk-size class
- * (chunks 2-8, 9-12, 13-16, 17-24, 25-32), in order on the caller's stream.
+ * (chunks 2-8, 9-12, 13-16, 17-24, 25-28, 29-30, 31, 32), in order on the
+ * caller's stream.
  * Either way the caller's stream is ordered after the whole batch. (The server's
  * launches, which overlap on streams of their own, keep both on one stream.)
  * ------------------------------------------------------------------------- */

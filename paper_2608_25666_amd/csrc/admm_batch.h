@@ -63,7 +63,9 @@ __device__ __forceinline__ void batch_body(const BatchKernelArgs& B) {
       const int nbytes = R.frag_f32_bytes + (GEMM == GEMM_F32 ? 0 : R.frag_16_bytes);
       const v4u* src = reinterpret_cast<const v4u*>(R.frag);
       v4u* dst = reinterpret_cast<v4u*>(lds);
-      for (int i = threadIdx.x; i < nbytes / 16; i += blockDim.x) dst[i] = src[i];
+      // index from the wave and lane ids (kWaves * 64 threads): the work-item id
+      // register need not stay live (at 256 registers the FP16 {5, 13} kernel spilled it)
+      for (int i = wave * 64 + (int)__lane_id(); i < nbytes / 16; i += kWaves * 64) dst[i] = src[i];
       __syncthreads();
       staged = R.frag;
     }
@@ -129,8 +131,10 @@ using BatchKernelFn = void (*)(BatchKernelArgs);
 
 // Kernels by chunk-size set: 0 = {5, 13} (horizons 17-20, 49-52; two waves per SIMD),
 // 6 = {25} (horizons 97-100; one wave), 1 = chunks 2..8, 2 = 9..12 (two waves),
-// 3 = 13..16, 4 = 17..24, 5 = 25..32 (one wave). A batch whose chunks all fall in
-// {5, 13, 25} runs sets 6 and 0; any other mix runs the classes 1..5 it uses.
+// 3 = 13..16, 4 = 17..24, 5 = 25..28, 7 = 29..30, 8 = 31, 9 = 32 (one wave; the last
+// four split so that no class needs scratch). A batch whose chunks all fall in {5, 13, 25}
+// runs sets 6 and 0; any other mix runs the classes it uses, in the order of kBatchClasses.
+constexpr int kBatchClasses[] = {1, 2, 3, 4, 5, 7, 8, 9};
 BatchKernelFn batch_kernel_f32(int set);
 BatchKernelFn batch_kernel_bf16(int set);
 BatchKernelFn batch_kernel_f16(int set);
@@ -142,8 +146,11 @@ inline bool batch_set_has(int set, int hq) {
     case 2: return hq >= 9 && hq <= 12;
     case 3: return hq >= 13 && hq <= 16;
     case 4: return hq >= 17 && hq <= 24;
-    case 5: return hq >= 25 && hq <= 32;
+    case 5: return hq >= 25 && hq <= 28;
     case 6: return hq == 25;
+    case 7: return hq == 29 || hq == 30;
+    case 8: return hq == 31;
+    case 9: return hq == 32;
     default: return false;
   }
 }

@@ -573,7 +573,13 @@ struct PairSolver {
     const bool reduced = GEMM != GEMM_F32;
     const int iters = A.iters;
     const int ce = A.check_every;
+    // reduced forms in residual mode, as in the one-wave tile: at the first check point
+    // whose residual exceeds kReducedRise times the lowest before it both members
+    // restart from the sample with a cold state in the FP32 form; after kReducedStall
+    // iterations with no new lowest residual they go on in FP32 as after convergence
     const int f32_from = !reduced ? 0 : (tolmode ? INT_MAX : iters - A.tail);
+    float rlow = __builtin_inff();
+    int it_low = 0;
     bool f32p = !reduced;
     int it = 0;
     int tail_end = -1;
@@ -598,6 +604,30 @@ struct PairSolver {
           }
         } else if (it == tail_end) {
           tail_end = -1;
+        }
+        if constexpr (GEMM != GEMM_F32) {
+          const float ru = __builtin_bit_cast(
+              float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, r)));
+          if (!f32p && it < iters) {
+            if (ru > kReducedRise * rlow) {
+#pragma unroll
+              for (int i = 0; i < 4 * NB; ++i) xb[i >> 2][i & 3] = (i < HP) ? xt[i * 64 + lane] : 0.0f;
+              if (m == 0 && g == 0) xb[0][0] = v0;
+#pragma unroll
+              for (int i = 0; i < HP; ++i) { qv[i] = 0.0f; qq[i] = 0.0f; qa[i] = 0.0f; qj[i] = 0.0f; }
+              prep = A.alpha != 1.0f;
+              f32p = true;
+              tail_end = -1;
+              continue;   // both members take this branch: the same tile residual
+            }
+            if (ru < rlow) {
+              rlow = ru;
+              it_low = it;
+            } else if (it - it_low >= kReducedStall) {
+              f32p = true;
+              tail_end = it + A.tail;
+            }
+          }
         }
       }
       if (it == iters) break;

@@ -405,6 +405,16 @@ struct TileSolver {
     }
   }
 
+  // Cold state from the sample held in LDS: x = x~ with x_1 = v0, q = (1 - alpha) C x.
+  __device__ __forceinline__ void restart_cold() {
+#pragma unroll
+    for (int i = 0; i < 4 * NB; ++i) xb[i >> 2][i & 3] = (i < HQ) ? xt_lds[i * 64 + lane] : 0.0f;
+    if (g == 0) xb[0][0] = v0;
+#pragma unroll
+    for (int i = 0; i < HQ; ++i) { qv[i] = 0.0f; qq[i] = 0.0f; qa[i] = 0.0f; qj[i] = 0.0f; }
+    if (oma != 0.0f) prep_q(oma, v0);
+  }
+
   // Advance a row block held as this lane's chunk (steps g*HQ .. g*HQ+HQ-1) by
   // one step: step k takes step k+1, the last step H-1 keeps its value, rows
   // past H stay zero. The chunk boundary comes from the next lane group.
@@ -556,7 +566,20 @@ struct TileSolver {
     // iterations follow (check points inside the tail do not stop it) and the tile
     // stops at the end of the tail if it still meets the tolerance there, else at the
     // first later check point that does (FP32 iterations, checked every check_every).
+    // Reduced forms in residual mode: the rounded x-update perturbs the iteration map,
+    // and near alpha = 2 that can outweigh the contraction, so that the iterates
+    // diverge, or hold them at a rounding floor above tol. A tile whose residual at a
+    // check point exceeds kReducedRise times the lowest it had at an earlier one
+    // (exact iterations rise by at most about 15x on the way down) restarts there from
+    // the sample with a cold state and the FP32 GEMM: from then on it runs the FP32
+    // form, which stops at the first check point that meets tol (continuing from the
+    // diverged state in FP32 was measured to need thousands of iterations). A tile
+    // whose residual has set no new low for kReducedStall iterations (exact iterations
+    // go at most about 130 without one) goes on from its state in FP32, as after
+    // convergence: `tail` iterations at least, then the first check point meeting tol.
     const int f32_from = !reduced ? 0 : (tolmode ? INT_MAX : iters - A.tail);
+    float rlow = __builtin_inff();   // lowest tile residual at the check points so far
+    int it_low = 0;                  // the check point that set it
     bool f32p = !reduced;
     int it = 0;
     int tail_end = -1;           // iteration that ends the FP32 tail after convergence
@@ -567,15 +590,37 @@ struct TileSolver {
       row_update<true>();
       if (tolmode) {
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
-        if (wave_max(r) <= A.tol) {
-          // FP32 form (tail_end -1), or the FP32 tail has run: done
-          if (A.tail <= 0 || (f32p && it >= tail_end)) break;
-          if (!f32p) {
-            f32p = true;
-            tail_end = it + A.tail;
+        if constexpr (GEMM == GEMM_F32) {
+          if (wave_max(r) <= A.tol) break;
+        } else {
+          // every lane holds the maximum; read back as uniform for the GEMM switch
+          const float rm = __builtin_bit_cast(
+              float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(r))));
+          if (rm <= A.tol) {
+            // the FP32 tail has run (or there is none): done
+            if (A.tail <= 0 || (f32p && it >= tail_end)) break;
+            if (!f32p) {
+              f32p = true;
+              tail_end = it + A.tail;
+            }
+          } else if (it == tail_end) {
+            tail_end = -1;
           }
-        } else if (it == tail_end) {
-          tail_end = -1;
+          if (!f32p && it < iters) {
+            if (rm > kReducedRise * rlow) {
+              restart_cold();
+              f32p = true;
+              tail_end = -1;
+              continue;   // rows of the restarted state at this check point
+            }
+            if (rm < rlow) {
+              rlow = rm;
+              it_low = it;
+            } else if (it - it_low >= kReducedStall) {
+              f32p = true;
+              tail_end = it + A.tail;
+            }
+          }
         }
       }
       if (it == iters) break;

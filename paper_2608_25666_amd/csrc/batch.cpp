@@ -132,7 +132,7 @@ prism_status_t enqueue_batch(prism_batch_s* b, const BatchDesc* reqs, int n_req,
           break;
         }
   } else {
-    for (int s = 1; s <= 5; ++s)
+    for (int s : kBatchClasses)
       for (int r : live)
         if (batch_set_has(s, reqs[r].p->HQ)) {
           sets.push_back(s);

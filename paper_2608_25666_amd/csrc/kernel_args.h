@@ -9,6 +9,11 @@ constexpr int kMaxJoints = 64;   // PRISM_MAX_JOINTS
 constexpr int kWaves = 4;        // waves per workgroup
 constexpr int kTileCols = 16;    // samples per tile (MFMA N dimension)
 constexpr int kXcdQueues = 8;    // tile queues, one per XCD (MI355X has 8)
+constexpr float kReducedRise = 64.0f;    // residual mode: a reduced-form tile whose residual
+                                          // rises this far above its lowest restarts in FP32
+constexpr int kReducedStall = 500;       // residual mode: a reduced-form tile with no new
+                                          // lowest residual for this many iterations goes on
+                                          // in FP32
 
 enum GemmPrec : int { GEMM_F32 = 0, GEMM_BF16 = 1, GEMM_F16 = 2 };
 

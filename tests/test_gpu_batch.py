@@ -87,6 +87,31 @@ def test_batch_mixed_chunk_classes():
     assert np.abs(b[0][:3] - O.x).max() <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_long_chunk_classes(prec):
+    """Horizons 99..128 (chunks 25, 28, 30, 31, 32) take the four one-wave classes
+    {25..28}, {29, 30}, {31}, {32}: per-request exact against the single solves, and
+    one request of each chunk against the oracle (FP32 bar; reduced forms at their
+    fixed-count bar)."""
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP32
+    from test_gpu_forms import TOL_BF16_TAIL
+    p = PREC_FP32 if prec == "fp32" else PREC_BF16
+    reqs = _small_mix(5, h_choices=(99, 110, 117, 121, 128), n_choices=(5, 16, 40), n_requests=8)
+    chunks = [(r.H + 3) // 4 for r in reqs]
+    assert sorted(set(chunks)) == [25, 28, 30, 31, 32]
+    o = options(alpha=1.6, precision=p, fp32_tail=0 if prec == "fp32" else 10)
+    batched, single, ws = _batch_and_single(reqs, 60, o)
+    _assert_same(batched, single)
+    for c in sorted(set(chunks)):
+        k = chunks.index(c)
+        r, b, w = reqs[k], batched[k], ws[k]
+        O = admm.solve_request(r.samples[:3], r.H, r.dt, r.bounds, r.q0, r.v0, iters=60,
+                               alpha=1.6, weights=w)
+        err = np.abs(b[0][:3] - O.x).max()
+        print(f"chunk {c} (H={r.H}) {prec}: max-abs {err:.3e}")
+        assert err <= (1e-4 if prec == "fp32" else TOL_BF16_TAIL)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_batch_reduced_precision_equals_single(prec):
     from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
@@ -248,6 +273,95 @@ def test_uneven_batch_bench_settings_sampled(prec):
                             xbar=1e-4 if prec == "fp32" else TOL_REDUCED_RESIDUAL,
                             check_stops=prec == "fp32",
                             label=f"uneven request {k} H={r.H} dt={r.dt} {prec}", joints=joints)
+    B.close()
+    for P in handles.values():
+        P.close()
+
+
+def test_reduced_form_divergence_restarts_in_fp32():
+    """Near alpha = 2 the BF16 x-update's rounding can outweigh the contraction: at 1.95
+    the iterates of some tiles of the uneven batch diverge (measured with no guard: NaN
+    on 5816 columns, also at a fixed 3000 iterations; at 1.9 on 17; FP32 and FP16 none).
+    In residual mode a tile whose residual rises 64x above its lowest restarts from the
+    sample with a cold state in the FP32 form. So every column is finite and meets the
+    tolerance; a restarted tile's result is bit for bit the FP32 form's, after a whole
+    number of check periods more iterations (the ones it abandoned); the slowest tile's
+    columns agree with the oracle run to the reported counts; and the same request alone
+    through the one-wave and the two-wave tile kernels does the same."""
+    import torch
+    from paper_2608_25666_amd import Batch, Projector, options, PREC_BF16, PREC_FP32
+    from stops import check_residual_mode
+    from test_gpu_forms import TOL_REDUCED_RESIDUAL
+    alpha, cap, ce = 1.95, 20000, 10
+    reqs = W.uneven_requests()
+    handles = {}
+    for r in reqs:
+        key = (r.H, r.nj, r.dt)
+        if key not in handles:
+            handles[key] = Projector(r.H, r.nj, r.dt, r.bounds, r.rho, weights="default")
+    xs = [torch.from_numpy(r.samples).cuda() for r in reqs]
+    B = Batch()
+
+    def run(prec):
+        its = [torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda") for r in reqs]
+        res = B.solve([dict(proj=handles[(r.H, r.nj, r.dt)], samples=x, q0=r.q0, v0=r.v0,
+                            iters=cap, iters_out=it) for r, x, it in zip(reqs, xs, its)],
+                      opts=options(precision=prec, alpha=alpha, tol=1e-3, check_every=ce,
+                                   fp32_tail=0 if prec == PREC_FP32 else 10))
+        torch.cuda.synchronize()
+        return [(x.cpu().numpy(), np.maximum(rp.cpu().numpy(), rd.cpu().numpy()), it.cpu().numpy())
+                for (x, rp, rd), it in zip(res, its)]
+
+    ref, red = run(PREC_FP32), run(PREC_BF16)
+    restarted, top = 0, (0, 0)
+    for k, (r, (xf, _, itf), (xb, res, itb)) in enumerate(zip(reqs, ref, red)):
+        assert not np.isnan(xb).any()
+        assert np.all(res <= 1e-3)
+        if itb.max() > top[0]:
+            top = (int(itb.max()), k)
+        for t0 in range(0, r.N, 16):
+            for j in range(r.nj):
+                cols = slice(t0, min(t0 + 16, r.N))
+                d = itb[cols, j] - itf[cols, j]
+                if np.array_equal(xb[cols, :, j], xf[cols, :, j]) and d[0] > 0:
+                    assert np.all(d == d[0]) and d[0] % ce == 0
+                    restarted += 1
+    print(f"alpha {alpha} bf16: tiles restarted in FP32 {restarted}, max iterations {top[0]} "
+          f"(request {top[1]})")
+    assert restarted > 0
+    assert top[0] < cap // 2     # measured 5620 (the cap was reached without the guards)
+    # the slowest tile against the oracle: a restarted one as the FP32 form it became
+    # (the oracle run to the FP32 counts, FP32 bar and stop points), else at the
+    # reduced form's residual-mode bar
+    k = top[1]
+    r = reqs[k]
+    xb, res, itg = red[k]
+    xf, _, itf = ref[k]
+    col, jnt = np.unravel_index(int(np.argmax(itg)), itg.shape)
+    rows = np.arange((col // 16) * 16, min((col // 16) * 16 + 16, r.N))
+    P = handles[(r.H, r.nj, r.dt)]
+    was_restarted = np.array_equal(xb[rows, :, jnt], xf[rows, :, jnt])
+    check_residual_mode(xb[rows], res[rows], res[rows], (itf if was_restarted else itg)[rows],
+                        rows, r.samples, r.H, r.dt, r.bounds, r.q0, r.v0, tol=1e-3,
+                        check_every=ce, cap=cap, alpha=alpha, weights=P.weights,
+                        xbar=1e-4 if was_restarted else TOL_REDUCED_RESIDUAL,
+                        check_stops=was_restarted,
+                        label=f"slowest tile of request {k} (H={r.H}, restarted {was_restarted})",
+                        joints=[int(jnt)])
+    for tw in (1, 2):
+        it = torch.zeros((r.N, r.nj), dtype=torch.int32, device="cuda")
+        x1, rp1, rd1 = P.solve(xs[k], r.q0, r.v0, cap, iters_out=it,
+                               opts=options(precision=PREC_BF16, alpha=alpha, tol=1e-3,
+                                            check_every=ce, fp32_tail=10, tile_waves=tw))
+        torch.cuda.synchronize()
+        x1 = x1.cpu().numpy()
+        assert not np.isnan(x1).any()
+        assert np.all(np.maximum(rp1.cpu().numpy(), rd1.cpu().numpy()) <= 1e-3)
+        print(f"request {k} alone, tile_waves {tw}: max iterations {int(it.max().item())}")
+        assert int(it.max().item()) < cap // 2
+        if tw == 1:
+            np.testing.assert_array_equal(x1, xb)
+            np.testing.assert_array_equal(it.cpu().numpy(), itg)
     B.close()
     for P in handles.values():
         P.close()
