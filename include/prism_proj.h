@@ -89,14 +89,18 @@ typedef struct {
                            0) exactly fp32_tail FP32 iterations follow (check points
                            inside them do not stop the group), and the group stops
                            at their end if it meets tol there, else at the first
-                           later check point that does, staying in FP32. A group
-                           whose max residual at a check point exceeds 64 times
-                           the lowest it had at an earlier one enters that FP32
-                           phase there (tail included): near alpha = 2 the
-                           rounded x-update can make the iterates diverge (BF16
-                           at alpha 1.9 and 1.95 measured; FP16 did not).
-                           Fixed-count runs have no such guard: keep alpha <=
-                           1.85 for BF16 there                                    */
+                           later check point that does, staying in FP32. Near
+                           alpha = 2 the rounded x-update can make the iterates
+                           diverge or stall above tol (BF16 at alpha 1.9 and
+                           1.95 measured; FP16 did not), so a group whose max
+                           residual at a check point exceeds 64 times the lowest
+                           it had before restarts from its samples with a cold
+                           state in the FP32 form (which stops at the first
+                           check point meeting tol; the reported count includes
+                           the abandoned iterations), and a group whose residual
+                           sets no new low for 500 iterations enters the FP32
+                           phase above from its state. Fixed-count runs have no
+                           such guard: keep alpha <= 1.85 for BF16 there         */
   float alpha;          /* over-relaxation in (0, 2); 1 = plain ADMM                 */
   float tol;            /* <= 0: run exactly `iters` iterations. > 0: each group of
                            16 samples of one joint stops at the first check point
