@@ -589,13 +589,15 @@ struct TileSolver {
     for (;;) {
       row_update<true>();
       if (tolmode) {
+        // Every lane holds the maximum; read back as uniform, the stop test and the GEMM
+        // switch are scalar branches, so the iteration counter and the inner loops stay
+        // scalar (with a per-lane maximum they became execution-masked vector loops).
         const float r = col_ok ? fmaxf(rpm, rdm) : 0.0f;
+        const float rm = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(r))));
         if constexpr (GEMM == GEMM_F32) {
-          if (wave_max(r) <= A.tol) break;
+          if (rm <= A.tol) break;
         } else {
-          // every lane holds the maximum; read back as uniform for the GEMM switch
-          const float rm = __builtin_bit_cast(
-              float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(r))));
           if (rm <= A.tol) {
             // the FP32 tail has run (or there is none): done
             if (A.tail <= 0 || (f32p && it >= tail_end)) break;
