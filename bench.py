@@ -151,14 +151,18 @@ def parse():
 
 
 def kernel_source_sha(literal: bool = False) -> str:
-    """sha256 over the device sources of a kernel, as recorded beside the rocprofv3
-    counters in profiles/traffic.json: kernel_args.h with admm_*.h and admm_*.hip for
-    the projection kernels (the two-wave tile sources admm_pair* excepted: the measured
-    launches do not include them), kernel_args.h with literal.hip for the printed
-    iteration."""
+    """sha256 over the device sources of a kernel and the compile flags, as recorded
+    beside the rocprofv3 counters in profiles/traffic.json: kernel_args.h with admm_*.h
+    and admm_*.hip for the projection kernels (the two-wave tile sources admm_pair*
+    excepted: the measured launches do not include them), kernel_args.h with literal.hip
+    for the printed iteration; the flags are the build's common hipcc options without
+    the include paths."""
     import hashlib
+    from paper_2608_25666_amd import build as B
     d = os.path.join(ROOT, "paper_2608_25666_amd", "csrc")
     h = hashlib.sha256()
+    flags = [a for i, a in enumerate(B.COMMON) if a != "-I" and (i == 0 or B.COMMON[i - 1] != "-I")]
+    h.update(" ".join(flags).encode())
     for f in sorted(os.listdir(d)):
         if literal:
             own = f in ("kernel_args.h", "literal.hip")
