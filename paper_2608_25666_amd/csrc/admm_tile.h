@@ -172,6 +172,10 @@ struct TileSolver {
     const float w = fmaf(2.0f, z, -q) - s;
     if constexpr (CHECK) { e = z - s; u = q - z; }
     q = fmaf(-alpha, z, q);                    // q' = t - alpha z
+    // On check iterations the stop test follows: keep q' computed here. Left free, the
+    // compiler sinks this update past the residual reduction, keeping t and z alive
+    // across it instead of q' (about 100 more registers at HQ = 25). Empty asm: no code.
+    if constexpr (CHECK) asm volatile("" : "+v"(q));
     return w;
   }
 
@@ -558,6 +562,9 @@ struct TileSolver {
     if ((A.uw == nullptr || shift) && A.alpha != 1.0f) prep_q(oma, v0);
 
     const bool tolmode = A.tolmode != 0;
+    // the tolerance as a uniform value: the batch kernel reads its arguments from a
+    // table in global memory, and a per-lane copy made the stop test a divergent branch
+    const float tol = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, A.tol)));
     const bool reduced = GEMM != GEMM_F32;
     const int iters = A.iters;
     const int ce = A.check_every;
@@ -596,9 +603,9 @@ struct TileSolver {
         const float rm = __builtin_bit_cast(
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(r))));
         if constexpr (GEMM == GEMM_F32) {
-          if (rm <= A.tol) break;
+          if (rm <= tol) break;
         } else {
-          if (rm <= A.tol) {
+          if (rm <= tol) {
             // the FP32 tail has run (or there is none): done
             if (A.tail <= 0 || (f32p && it >= tail_end)) break;
             if (!f32p) {
