@@ -98,11 +98,18 @@ __global__ __launch_bounds__(256) void admm_solve_kernel(SolveKernelArgs A) {
   solve_body<HQ, EXACT, GEMM>(A);
 }
 
+// Eight waves per workgroup (solve_waves): two per SIMD, one staged factor for all.
+template <int HQ, bool EXACT, int GEMM>
+__global__ __launch_bounds__(512) void admm_solve_kernel_8w(SolveKernelArgs A) {
+  solve_body<HQ, EXACT, GEMM>(A);
+}
+
 using SolveKernelFn = void (*)(SolveKernelArgs);
 
 template <int HQ, bool EXACT, int GEMM>
 SolveKernelFn kernel_for() {
   if constexpr (HQ <= kMaxHQTwoWaves) return admm_solve_kernel_2w<HQ, EXACT, GEMM>;
+  else if constexpr (solve_waves(HQ, GEMM != GEMM_F32) == 8) return admm_solve_kernel_8w<HQ, EXACT, GEMM>;
   else return admm_solve_kernel<HQ, EXACT, GEMM>;
 }
 

@@ -7,6 +7,11 @@ namespace prism {
 
 constexpr int kMaxJoints = 64;   // PRISM_MAX_JOINTS
 constexpr int kWaves = 4;        // waves per workgroup
+// Waves per workgroup of a single-solve launch. The reduced forms with chunks 22..25
+// (H = 85..100) fit in 256 registers, but a four-wave workgroup's staged factor and
+// samples (about 104 KB of LDS at chunk 25) leave room for one workgroup per CU; eight
+// waves sharing one staged factor (about 129 KB) run two waves per SIMD instead.
+constexpr int solve_waves(int HQ, bool reduced) { return (reduced && HQ >= 22 && HQ <= 25) ? 8 : kWaves; }
 constexpr int kTileCols = 16;    // samples per tile (MFMA N dimension)
 constexpr int kXcdQueues = 8;    // tile queues, one per XCD (MI355X has 8)
 constexpr float kReducedRise = 64.0f;    // residual mode: a reduced-form tile whose residual

@@ -64,16 +64,17 @@ void release_literal_factors(prism_proj_s* p);
 prism_status_t fill_joint_params(const prism_proj_s* p, const double* q0, const double* v0,
                                  JointRowParams* jp);
 SolveKernelFn pick_kernel(int HQ, bool exact, int precision);
-int solve_lds_bytes(const prism_proj_s* p, int precision);
+int solve_lds_bytes(const prism_proj_s* p, int precision, int waves);
 int solve_frag_bytes(const prism_proj_s* p, int precision);
 prism_status_t validate_options(const prism_options_t* o);
 int kernel_blocks_per_cu(const void* fn, int lds_bytes);
 // Fills the solver fields of K (the caller sets samples, outputs, N, iters, jp and
 // the optional sampling / cost parts), clears the tile queues and launches fn.
 // counters: kXcdQueues device ints owned by the caller, or null to take a set from
-// the handle's ring.
+// the handle's ring. waves: the kernel's waves per workgroup (its launch bound / 64).
 prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
-                            SolveKernelFn fn, hipStream_t stream, int* counters = nullptr);
+                            SolveKernelFn fn, hipStream_t stream, int* counters = nullptr,
+                            int waves = kWaves);
 prism_status_t check_device(const prism_proj_s* p);   // occupancy, cached per (kernel, LDS)
 int device_cus();
 

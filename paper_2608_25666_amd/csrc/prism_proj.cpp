@@ -55,14 +55,14 @@ int num_cus() {
   return g_num_cu;
 }
 
-int blocks_per_cu(const void* fn, int lds) {
+int blocks_per_cu(const void* fn, int lds, int threads = kWaves * 64) {
   std::lock_guard<std::mutex> lk(g_occ_mu);
-  auto& m = g_occ[fn];
+  auto& m = g_occ[fn];   // a kernel is always launched with the same thread count
   auto it = m.find(lds);
   if (it != m.end()) return it->second.blocks_per_cu;
   if (lds > 64 * 1024) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess || nb <= 0) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess || nb <= 0) nb = 1;
   m[lds].blocks_per_cu = nb;
   return nb;
 }
@@ -143,12 +143,12 @@ int solve_frag_bytes(const prism_proj_s* p, int precision) {
   return p->f32_bytes + (precision == PRISM_PREC_FP32 ? 0 : p->b16_bytes);
 }
 
-int solve_lds_bytes(const prism_proj_s* p, int precision) {
-  return solve_frag_bytes(p, precision) + kWaves * p->HQ * 64 * (int)sizeof(float);
+int solve_lds_bytes(const prism_proj_s* p, int precision, int waves) {
+  return solve_frag_bytes(p, precision) + waves * p->HQ * 64 * (int)sizeof(float);
 }
 
 prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_options_t* o,
-                            SolveKernelFn fn, hipStream_t stream, int* counters) {
+                            SolveKernelFn fn, hipStream_t stream, int* counters, int waves) {
   const int tiles_per_joint = (K.N + kTileCols - 1) / kTileCols;
   const long long ntiles = (long long)tiles_per_joint * p->nj;
   if (ntiles > 0x7fffffff) return PRISM_EINVAL;
@@ -167,9 +167,9 @@ prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_opt
   K.tol = o->tol;
   K.frag_f32_bytes = p->f32_bytes;
   K.frag_16_bytes = p->b16_bytes;
-  const int lds = solve_lds_bytes(p, o->precision);
-  const int bpc = blocks_per_cu((const void*)fn, lds);
-  const long long want = (ntiles + kWaves - 1) / kWaves;
+  const int lds = solve_lds_bytes(p, o->precision, waves);
+  const int bpc = blocks_per_cu((const void*)fn, lds, waves * 64);
+  const long long want = (ntiles + waves - 1) / waves;
   const long long cap = (long long)bpc * num_cus();
   const int grid = (int)std::max(1ll, std::min(want, cap));
 
@@ -177,7 +177,7 @@ prism_status_t launch_solve(prism_proj_s* p, SolveKernelArgs& K, const prism_opt
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, K.counter);
     if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
     void* params[] = {&K};
-    if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(kWaves * 64), params, lds, stream) !=
+    if (hipLaunchKernel((const void*)fn, dim3(grid), dim3(waves * 64), params, lds, stream) !=
         hipSuccess)
       return PRISM_EDEVICE;
     if (hipGetLastError() != hipSuccess) return PRISM_EDEVICE;
@@ -535,7 +535,7 @@ prism_status_t prism_proj_solve_ex(prism_proj_t p, const prism_solve_args_t* a, 
   K.N = a->N;
   K.iters = a->iters;
   if (pfn) return launch_pair(p, K, o, pfn, stream);
-  return launch_solve(p, K, o, fn, stream);
+  return launch_solve(p, K, o, fn, stream, nullptr, solve_waves(p->HQ, o->precision != PRISM_PREC_FP32));
 }
 
 prism_status_t prism_proj_solve(prism_proj_t p, const float* v_samples, int N, const double* q0,

@@ -112,6 +112,34 @@ def test_batch_long_chunk_classes(prec):
         assert err <= (1e-4 if prec == "fp32" else TOL_BF16_TAIL)
 
 
+@pytest.mark.parametrize("tol", [0.0, 1e-3])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_eight_wave_single_solves_equal_batch(prec, tol):
+    """Single solves of the reduced forms at chunks 22..25 (H = 86, 90, 93, 97; ragged
+    rows) run eight waves per workgroup; the batch runs the same tile code four waves per
+    workgroup. Per request bit-identical, fixed count and residual mode; one request
+    against the oracle at the fixed count."""
+    from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
+    from test_gpu_forms import TOL_BF16_TAIL
+    from test_gpu_pair import TOL_F16_FIXED   # FP16 at a fixed count, alpha 1.8
+    p = PREC_BF16 if prec == "bf16" else PREC_FP16
+    reqs = _small_mix(11, h_choices=(86, 90, 93, 97), n_choices=(16, 37, 300), n_requests=8)
+    assert sorted({(r.H + 3) // 4 for r in reqs}) == [22, 23, 24, 25]
+    o = options(precision=p, fp32_tail=10, alpha=1.8, tol=tol)
+    batched, single, ws = _batch_and_single(reqs, 2000 if tol > 0 else 100, o, with_iters=True)
+    _assert_same(batched, single)
+    if tol == 0.0:
+        r, b, w = reqs[0], batched[0], ws[0]
+        O = admm.solve_request(r.samples[:4], r.H, r.dt, r.bounds, r.q0, r.v0, iters=100,
+                               alpha=1.8, weights=w)
+        err = np.abs(b[0][:4] - O.x).max()
+        print(f"H={r.H} {prec}: max-abs {err:.3e}")
+        assert err <= (TOL_BF16_TAIL if prec == "bf16" else TOL_F16_FIXED)
+    else:
+        for b in batched:
+            assert np.all(np.maximum(b[1], b[2]) <= 1e-3)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_batch_reduced_precision_equals_single(prec):
     from paper_2608_25666_amd import options, PREC_BF16, PREC_FP16
