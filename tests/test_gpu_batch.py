@@ -311,7 +311,9 @@ def test_reduced_form_divergence_restarts_in_fp32():
     the iterates of some tiles of the uneven batch diverge (measured with no guard: NaN
     on 5816 columns, also at a fixed 3000 iterations; at 1.9 on 17; FP32 and FP16 none).
     In residual mode a tile whose residual rises 64x above its lowest restarts from the
-    sample with a cold state in the FP32 form. So every column is finite and meets the
+    sample with a cold state in the FP32 form, and one whose residual sets no new low
+    for 500 iterations goes on in FP32 (with the restart rule alone, 213,832 columns
+    still stalled above tol until the cap). So every column is finite and meets the
     tolerance; a restarted tile's result is bit for bit the FP32 form's, after a whole
     number of check periods more iterations (the ones it abandoned); the slowest tile's
     columns agree with the oracle run to the reported counts; and the same request alone
